@@ -1,0 +1,200 @@
+"""Benchmark: effective memory throughput of the PT iteration at 511^3.
+
+One "step" is one PT iteration of the thesis schedule (article 1, section 2.2;
+appendix two-phase script) on the 511^3 porosity-anomaly workload (two
+Gaussian anomalies, lognormal k0, Drucker-Prager cap), FP64: the fused sweep
+updates all velocities, both pressures and the porosity every iteration, the
+lagged coefficients are refreshed every nup = 15 iterations and the residual
+norms taken every nup iterations (both amortised in the timing, as the thesis's
+t_it = time/niter does).
+
+value = T_eff = A_eff / t_it with A_eff = (2*12 + 1) N p (eqs (37)-(38)),
+N = 511^3 cells, p = 8 bytes.
+
+Prints one JSON line.  Options: --gpus N (only 1: the build runs on one GPU),
+--steps K, --warmup W, --n (grid size), --no-cpu (skip the CPU baseline).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "PT-iter T_eff GB/s (% HBM peak) at 511³; mixed vs FP64 time-to-tol 1e-8"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_iter_thesis_511.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2207_08716_amd", "csrc", "iter_kernel.hip")
+
+
+def kernel_source_sha() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(n: int):
+    """HBM bytes per launch of the dominant kernel from committed rocprofv3
+    counter runs, if they were taken on the current kernel source."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha") != kernel_source_sha() or rec.get("n") != n:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(cfg, fields, n_iter: int = 2):
+    """The FP64 CPU reference timed on this host: thesis schedule on the same
+    511^3 workload, a bounded sample of n_iter iterations after the first
+    (refreshing) one."""
+    import oracle
+    from paper_2207_08716_amd import teff
+    t0 = time.perf_counter()
+    o = oracle.Oracle(cfg.phys, cfg.nx, cfg.ny, cfg.nz, fields["phi"], fields["k0"])
+    o.begin_step()
+    o.iterate(1)
+    t1 = time.perf_counter()
+    o.iterate(n_iter)
+    t2 = time.perf_counter()
+    t_it = (t2 - t1) / n_iter
+    del o
+    return {
+        "value": round(teff.t_eff_gbs(cfg.ncell, 8, t_it), 3),
+        "unit": "GB/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": f"{n_iter} thesis-schedule PT iterations of the same {cfg.nx}^3 FP64 workload "
+                  f"after one warm-up iteration (setup {t1 - t0:.1f} s); t_it = {t_it:.3f} s",
+        "t_it_s": t_it,
+    }
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=150)
+    ap.add_argument("--warmup", type=int, default=30)
+    ap.add_argument("--n", type=int, default=511)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=2)
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this solver runs on one GPU; multi-GPU runs are not part of this build "
+              f"(asked for --gpus {args.gpus})", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2207_08716_amd import inputs, schedules, teff
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        return 1
+
+    n = args.n
+    cfg = inputs.config_mixed(n)
+    fields = inputs.initial_fields(cfg)
+    g = schedules.make_grid(cfg, fields)
+    s = g.stream
+    a_eff = teff.a_eff_bytes(cfg.ncell, 8)
+
+    def timed(fn, reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        fn(reps)
+        e1.record(s)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / 1e3
+
+    # ---- warm-up: first refresh, then W thesis iterations ------------------
+    g.begin_step(update_history=False)
+    g.iterate(args.warmup)
+    torch.cuda.synchronize()
+
+    # ---- timed region: exactly K thesis-schedule iterations ----------------
+    torch.cuda.synchronize()
+    t_wall0 = time.perf_counter()
+    t_steps = timed(lambda k: g.iterate(k), args.steps)
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall0
+    norms = g.last_norms() if args.steps + args.warmup >= cfg.phys.nup else None
+    t_it = t_steps / args.steps
+    value = teff.t_eff_gbs(cfg.ncell, 8, t_it)
+
+    # ---- dominant kernel alone: the fused sweep (thesis variant), measured
+    # with HIP events on the solver's stream over back-to-back launches ------
+    k_reps = 45
+    t_sweep = timed(lambda k: [g.iteration(update_lp=True, norms=False) for _ in range(k)], k_reps) / k_reps
+    # linear (Picard-stage) variant of the sweep: porosity frozen
+    t_lin = timed(lambda k: [g.iteration(update_lp=False, norms=False) for _ in range(k)], k_reps) / k_reps
+
+    # ---- achievable HBM bandwidth: streaming copy of one field --------------
+    src = g.buf["kc"][0].view(-1)
+    dst = g.ws.new_empty(src.numel())
+    g.copy(src, dst)
+    t_copy = timed(lambda k: [g.copy(src, dst) for _ in range(k)], 20) / 20
+    copy_gbs = 2 * src.numel() * 8 / t_copy / 1e9
+    del dst
+    torch.cuda.synchronize()
+
+    achieved = a_eff / t_sweep / 1e9
+    traffic = measured_traffic(n)
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_it * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{n}^3 two-anomaly porosity grid, lognormal k0 (sigma 0.5), "
+                        "Drucker-Prager cap C=1 30deg, thesis PT schedule (refresh/norms every 15)",
+            "n": n, "cells": cfg.ncell, "precision": "fp64", "schedule": "thesis",
+            "parallelism": "single GPU",
+        },
+        "pct_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2),
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "k_iter<update_lp=true,norms=false> (fused PT sweep)",
+            "achieved": round(achieved, 2),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": a_eff,
+            "avg_launch_ms": round(t_sweep * 1e3, 4),
+        },
+        "linear_sweep": {"t_it_ms": round(t_lin * 1e3, 4),
+                         "t_eff_gbs": round(a_eff / t_lin / 1e9, 2)},
+        "copy_gbs": round(copy_gbs, 1),
+        "wall_s_timed": round(t_wall, 3),
+        "norms_last_check": norms,
+        "kernel_source_sha": kernel_source_sha(),
+    }
+    g.close()
+    del g
+    torch.cuda.empty_cache()
+
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(cfg, fields, args.cpu_iters)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,208 @@
+/*
+ * ptporo.h -- C ABI of the MI355X (gfx950) pseudo-transient solver for 3D
+ * poro-visco-elastic two-phase flow.
+ *
+ * The method is the pseudo-transient (PT) iteration of thesis article 1,
+ * section 2.2: the residual system of eqs (17)-(22) with the closures
+ * (23)-(27), advanced by the explicit update of eq (16) with the pressures'
+ * local terms implicit, damped solid velocities and porosity in log space,
+ * on the staggered grid of Fig. 1, with the boundary conditions of
+ * eqs (33)-(34) (zero normal velocity, zero normal Darcy flux, free slip).
+ * Coefficients k(phi), eta_phi(phi, R) and mu_s are lagged and refreshed
+ * (Picard); the solver stops on the one-iteration change of the thesis or on
+ * a relative residual.
+ *
+ * Conventions (all entry points)
+ * ------------------------------
+ * Ownership.  The caller owns every device buffer and the stream; the library
+ *   owns only the handle.  It never allocates device memory: the scratch it
+ *   needs (per-block partial maxima) is a caller buffer bound with
+ *   pt_bind_workspace.  Bound pointers must stay valid while the handle uses
+ *   them.
+ * Layout.  Every field is an FP64 array in one common padded box layout:
+ *   element (i, j, k) of any staggered field is at offset
+ *   (k * (ny + 1) + j) * row_pitch + i, x fastest, so each field buffer holds
+ *   pt_field_elems() doubles.  Cells use i < nx, j < ny, k < nz; x-faces
+ *   i <= nx; y-faces j <= ny; z-faces k <= nz; xy-edges i <= nx, j <= ny;
+ *   xz-edges i <= nx, k <= nz; yz-edges j <= ny, k <= nz.  Entries outside a
+ *   field's extent are never read or written.  Base pointers must be 256-byte
+ *   aligned; row_pitch >= nx + 1.
+ * State.  The nine iterated fields (PT_VX .. PT_RZ) are double-buffered
+ *   (Jacobi iteration: no point reads a value written in the same sweep).
+ *   Bind both copies (copy 0 and 1); pt_current() tells which copy holds the
+ *   present state.  Boundary-normal faces of V and R must hold zero in both
+ *   copies; the library never writes them.
+ * Synchrony.  Calls that launch work only enqueue it on the bound stream
+ *   (default: the null stream), except where marked "synchronises".
+ * Errors.  Every call returns a pt_status and never throws.  PT_EINVAL: a
+ *   bad argument (nothing was launched).  PT_EDEVICE: a HIP error.
+ *   PT_EDIVERGED: a non-finite norm.  PT_ENOTCONV: an iteration limit was
+ *   hit (the state is valid).  pt_last_error() holds a message for the last
+ *   failure on the handle.
+ * Threads.  One handle must not be used by two threads at once; distinct
+ *   handles are independent.
+ */
+#ifndef PTPORO_H
+#define PTPORO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PT_ABI_VERSION 1
+
+typedef struct pt_grid pt_grid;
+
+typedef enum {
+    PT_OK = 0,
+    PT_ENOTCONV = 1,
+    PT_EINVAL = -1,
+    PT_EDEVICE = -2,
+    PT_EDIVERGED = -3,
+    PT_EDOMAIN = -4,
+    PT_ESTATE = -5
+} pt_status;
+
+/* Field identifiers.  The first PT_NPING are double-buffered. */
+typedef enum {
+    PT_VX = 0, PT_VY, PT_VZ,        /* solid velocity, x/y/z-faces                    */
+    PT_PT, PT_PF,                   /* total and fluid pressure (cells)               */
+    PT_LP,                          /* ln(1 - phi) (cells)                            */
+    PT_RX, PT_RY, PT_RZ,            /* damped momentum residual, faces                */
+    PT_PTO, PT_PFO, PT_LPO,         /* previous-step Pt, Pf, ln(1-phi) (cells)        */
+    PT_SXX, PT_SYY, PT_SZZ,         /* stress history, cells                          */
+    PT_SXY, PT_SXZ, PT_SYZ,         /* stress history, xy/xz/yz-edges                 */
+    PT_FOX, PT_FOY, PT_FOZ,         /* divergence of the relaxed stress history, faces */
+    PT_MN,                          /* lagged shear-viscosity factor (cells)          */
+    PT_K0,                          /* per-cell k0/mu_f (cells; only with PT_F_K0FIELD) */
+    PT_KC,                          /* lagged k/mu_f (cells)                          */
+    PT_ETA,                         /* lagged bulk viscosity eta_phi (cells)          */
+    PT_MUS,                         /* lagged solid shear viscosity mu_s (cells)      */
+    PT_NFIELDS
+} pt_field;
+
+#define PT_NPING 9
+
+/* Flags of pt_params.flags */
+#define PT_F_POWERLAW 1u   /* eq (24): mu_s = mu0 / (1 + (tau_II/tau0)^(n-1))        */
+#define PT_F_DPCAP    2u   /* Drucker-Prager cap of the lagged viscosity             */
+#define PT_F_K0FIELD  4u   /* k0 is the per-cell field PT_K0, else the scalar kmuf0   */
+#define PT_F_MECHOFF  8u   /* freeze V and Pt (linear fluid-pressure diffusion limit) */
+
+/* Non-dimensional physical and numerical parameters (article 1, Table 2 and
+ * the appendix two-phase script; the readings of ambiguous values are listed
+ * in the design notes). */
+typedef struct {
+    int32_t version;                /* must be PT_ABI_VERSION                          */
+    uint32_t flags;                 /* PT_F_*                                          */
+    double lx, ly, lz;              /* domain size                                     */
+    double phi0;                    /* background porosity                             */
+    double kmuf0;                   /* k0 / mu_f (scalar)                              */
+    double eta0, mu0, cmu;          /* bulk-viscosity factor, shear factor, mu_s = Mn phi0 cmu */
+    double rhofg, rhosg;            /* fluid, solid density x gravity (z up)           */
+    double beta_phi, beta_d;        /* 1/K_phi, 1/K_d                                  */
+    double alpha, B;                /* Biot-Willis, Skempton                           */
+    double G;                       /* shear modulus                                   */
+    double R0;                      /* decompaction weakening factor (Pf > Pt)         */
+    double n_pow, tau0;             /* power-law exponent and stress                   */
+    double coh, fric_deg, tau_y_min;/* Drucker-Prager cohesion, friction angle, floor  */
+    double dt, dtS;                 /* physical step, stress-history step              */
+    double beta_n;                  /* numerical compressibility                       */
+    double rho_i;                   /* inertial density of the velocity update         */
+    double c_v, c_pf;               /* pseudo-step safety factors                      */
+    double damp_c;                  /* velocity damping d = 1 - damp_c / n             */
+    int32_t nup;                    /* iterations between refreshes / checks           */
+    int32_t pad_;
+    double r_eta, r_mu;             /* log-relaxation of the thesis schedule           */
+} pt_params;
+
+/* Residual norms and one-iteration changes (all infinity norms).
+ *   f    : max |momentum residual| (no numerical compressibility, current Pt)
+ *   rpt  : max |r_Pt|      rpf : max |r_Pf|        (eqs (17), (18))
+ *   dl, dpt, dpf, dvz, dv : max change of ln(1-phi), Pt, Pf, Vz, |V| over
+ *          the last checked iteration (the thesis's stopping quantity). */
+typedef struct {
+    double f, rpt, rpf, dl, dpt, dpf, dvz, dv;
+} pt_norms;
+
+/* Create a handle for an nx x ny x nz cell grid (each >= 2) with the given
+ * row pitch (>= nx + 1, in elements) and parameters (copied). */
+pt_status pt_create(int32_t nx, int32_t ny, int32_t nz, int64_t row_pitch,
+                    const pt_params* params, pt_grid** out);
+pt_status pt_destroy(pt_grid* g);
+
+/* Elements per field buffer: (nz + 1) * (ny + 1) * row_pitch. */
+int64_t pt_field_elems(const pt_grid* g);
+
+/* Bind a device buffer of pt_field_elems() doubles to a field.  copy is 0 or
+ * 1 for the double-buffered fields (PT_VX .. PT_RZ) and 0 otherwise. */
+pt_status pt_bind_field(pt_grid* g, int32_t field, int32_t copy, void* dev_ptr);
+
+/* Scratch for per-block partial maxima: query the size, then bind a device
+ * buffer of at least that many bytes (256-byte aligned). */
+pt_status pt_workspace_size(const pt_grid* g, size_t* bytes);
+pt_status pt_bind_workspace(pt_grid* g, void* dev_ptr, size_t bytes);
+
+/* Stream for all launches (a hipStream_t; NULL = the null stream). */
+pt_status pt_set_stream(pt_grid* g, void* hip_stream);
+pt_status pt_set_params(pt_grid* g, const pt_params* params);
+
+/* Which copy (0/1) of a double-buffered field holds the present state. */
+pt_status pt_current(const pt_grid* g, int32_t field, int32_t* copy);
+
+/* Start of a physical step (thesis script, per-step block): Pto <- Pt,
+ * Pfo <- Pf, ln(1-phi)o <- ln(1-phi); if update_history, the stress
+ * history becomes the deviatoric stress of the present state (eq (21)
+ * without the numerical-compressibility term) and the folded history term
+ * Fo is recomputed.  Resets the within-step iteration counter. */
+pt_status pt_begin_step(pt_grid* g, int32_t update_history);
+
+/* Picard refresh of the lagged coefficients from the present state
+ * (eqs (23)-(26), decompaction switch of eq (25), optional power law and
+ * Drucker-Prager cap), with log relaxation weights r_eta, r_mu (1 = none);
+ * the first refresh of a handle never relaxes.  Recomputes mu_s and Fo. */
+pt_status pt_refresh(pt_grid* g, double r_eta, double r_mu);
+
+/* One fused PT iteration (eq (16) applied to eqs (17)-(22)).
+ * update_porosity = 1 also advances ln(1-phi) (thesis schedule), 0 keeps
+ * it frozen (linear Picard stage).  want_norms = 1 computes the residual
+ * norms at the incoming state and the one-iteration changes (read them with
+ * pt_last_norms). */
+pt_status pt_iteration(pt_grid* g, int32_t update_porosity, int32_t want_norms);
+
+/* n iterations of the thesis schedule, continuing the step's count: a
+ * refresh with the relaxation of pt_params before iterations with
+ * (iter - 1) % nup == 0, norms on iterations with iter % nup == 0. */
+pt_status pt_iterate(pt_grid* g, int64_t n);
+
+/* Norms of the last iteration that computed them.  Synchronises. */
+pt_status pt_last_norms(pt_grid* g, pt_norms* out);
+
+/* Linear PT solve with coefficients and porosity frozen, until
+ * rho = max(g_V / g_V0, g_P / g_P0) <= rtol (g_V = max|f|,
+ * g_P = max(|r_Pt|, |r_Pf|), 0 = first iteration of this solve; groups with
+ * zero initial norm are dropped), checked every nup iterations, or max_iter.
+ * Synchronises.  Returns PT_ENOTCONV at max_iter. */
+pt_status pt_solve_linear(pt_grid* g, double rtol, int64_t max_iter,
+                          int64_t* iters, double* rho);
+
+/* Porosity time step after a converged Picard stage: ln(1-phi) =
+ * ln(1-phi)o - dt dphi/dt(V, Pt, Pf) (eq (22)) with the present solid
+ * fraction. */
+pt_status pt_porosity_step(pt_grid* g);
+
+/* Streaming copy of n doubles (achievable-bandwidth reference). */
+pt_status pt_copy(pt_grid* g, const void* src, void* dst, int64_t n);
+
+const char* pt_status_str(pt_status s);
+const char* pt_last_error(const pt_grid* g);
+int32_t pt_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PTPORO_H */

@@ -92,6 +92,7 @@ def _load():
         lib.or_tau_ii.argtypes = [C.c_void_p, P(_State), P(C.c_double)]
         lib.or_last_stresses.argtypes = [C.c_void_p] + [P(C.c_double)] * 6
         lib.or_last_fluxes.argtypes = [C.c_void_p] + [P(C.c_double)] * 3
+        lib.or_num_threads.restype = C.c_int
         lib.or_heat1d_step.restype = C.c_int
         lib.or_heat1d_step.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double,
                                        C.c_double, P(C.c_double), P(C.c_double), C.c_int]
@@ -292,6 +293,11 @@ def rel_residual(gv, gp, g0):
     if g0[1] > 0:
         r = max(r, gp / g0[1])
     return r
+
+
+def num_threads() -> int:
+    """Threads the oracle's OpenMP loops use."""
+    return int(_load().or_num_threads())
 
 
 def heat1d_step(Ut, U0, dx, dt, lam_rho_cp, eps, max_iter=10_000_000):

@@ -133,6 +133,19 @@ void or_destroy(or_ctx *c)
 
 int or_abi_version(void) { return OR_ABI_VERSION; }
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+/* Number of threads the OpenMP loops use. */
+int or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 /* Background density x gravity: rho_bg g = phi0 rho_f g + (1-phi0) rho_s g
  * (the script's rogBG).  Pressures are perturbations from the lithostatic
  * state of this density. */

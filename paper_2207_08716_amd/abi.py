@@ -1,0 +1,118 @@
+"""ctypes declarations of the C ABI in include/ptporo.h (marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libptporo.so")
+
+ABI_VERSION = 1
+
+FIELDS = ("vx", "vy", "vz", "pt", "pf", "lp", "rx", "ry", "rz", "pto", "pfo", "lpo",
+          "sxx", "syy", "szz", "sxy", "sxz", "syz", "fox", "foy", "foz", "mn", "k0",
+          "kc", "eta", "mus")
+FIELD_ID = {n: i for i, n in enumerate(FIELDS)}
+NPING = 9
+
+F_POWERLAW, F_DPCAP, F_K0FIELD, F_MECHOFF = 1, 2, 4, 8
+
+STATUS = {0: "PT_OK", 1: "PT_ENOTCONV", -1: "PT_EINVAL", -2: "PT_EDEVICE",
+          -3: "PT_EDIVERGED", -4: "PT_EDOMAIN", -5: "PT_ESTATE"}
+
+
+class Params(C.Structure):
+    _fields_ = [("version", C.c_int32), ("flags", C.c_uint32),
+                ("lx", C.c_double), ("ly", C.c_double), ("lz", C.c_double),
+                ("phi0", C.c_double), ("kmuf0", C.c_double),
+                ("eta0", C.c_double), ("mu0", C.c_double), ("cmu", C.c_double),
+                ("rhofg", C.c_double), ("rhosg", C.c_double),
+                ("beta_phi", C.c_double), ("beta_d", C.c_double),
+                ("alpha", C.c_double), ("B", C.c_double), ("G", C.c_double), ("R0", C.c_double),
+                ("n_pow", C.c_double), ("tau0", C.c_double),
+                ("coh", C.c_double), ("fric_deg", C.c_double), ("tau_y_min", C.c_double),
+                ("dt", C.c_double), ("dtS", C.c_double), ("beta_n", C.c_double),
+                ("rho_i", C.c_double), ("c_v", C.c_double), ("c_pf", C.c_double),
+                ("damp_c", C.c_double), ("nup", C.c_int32), ("pad_", C.c_int32),
+                ("r_eta", C.c_double), ("r_mu", C.c_double)]
+
+
+class Norms(C.Structure):
+    _fields_ = [(n, C.c_double) for n in ("f", "rpt", "rpf", "dl", "dpt", "dpf", "dvz", "dv")]
+
+
+EXPORTS = ["pt_create", "pt_destroy", "pt_field_elems", "pt_bind_field", "pt_workspace_size",
+           "pt_bind_workspace", "pt_set_stream", "pt_set_params", "pt_current", "pt_begin_step",
+           "pt_refresh", "pt_iteration", "pt_iterate", "pt_last_norms", "pt_solve_linear",
+           "pt_porosity_step", "pt_copy", "pt_status_str", "pt_last_error", "pt_abi_version"]
+
+_lib = None
+
+
+class PTError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def load(path: str = LIB_PATH):
+    """Load libptporo.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"HIP library not built: {path} (run __graft_entry__.build())")
+    lib = C.CDLL(path)
+    P = C.POINTER
+    vp = C.c_void_p
+    lib.pt_create.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int64, P(Params), P(vp)]
+    lib.pt_destroy.argtypes = [vp]
+    lib.pt_field_elems.argtypes = [vp]
+    lib.pt_field_elems.restype = C.c_int64
+    lib.pt_bind_field.argtypes = [vp, C.c_int32, C.c_int32, vp]
+    lib.pt_workspace_size.argtypes = [vp, P(C.c_size_t)]
+    lib.pt_bind_workspace.argtypes = [vp, vp, C.c_size_t]
+    lib.pt_set_stream.argtypes = [vp, vp]
+    lib.pt_set_params.argtypes = [vp, P(Params)]
+    lib.pt_current.argtypes = [vp, C.c_int32, P(C.c_int32)]
+    lib.pt_begin_step.argtypes = [vp, C.c_int32]
+    lib.pt_refresh.argtypes = [vp, C.c_double, C.c_double]
+    lib.pt_iteration.argtypes = [vp, C.c_int32, C.c_int32]
+    lib.pt_iterate.argtypes = [vp, C.c_int64]
+    lib.pt_last_norms.argtypes = [vp, P(Norms)]
+    lib.pt_solve_linear.argtypes = [vp, C.c_double, C.c_int64, P(C.c_int64), P(C.c_double)]
+    lib.pt_porosity_step.argtypes = [vp]
+    lib.pt_copy.argtypes = [vp, vp, vp, C.c_int64]
+    lib.pt_status_str.argtypes = [C.c_int]
+    lib.pt_status_str.restype = C.c_char_p
+    lib.pt_last_error.argtypes = [vp]
+    lib.pt_last_error.restype = C.c_char_p
+    lib.pt_abi_version.restype = C.c_int32
+    for name in EXPORTS:
+        if name not in ("pt_status_str", "pt_last_error", "pt_field_elems", "pt_abi_version"):
+            getattr(lib, name).restype = C.c_int
+    if lib.pt_abi_version() != ABI_VERSION:
+        raise ImportError("libptporo.so ABI version mismatch")
+    _lib = lib
+    return lib
+
+
+def params_from(phys, k0field: bool) -> Params:
+    """Marshal a Physics record into the C struct."""
+    p = Params()
+    p.version = ABI_VERSION
+    flags = 0
+    if phys.powerlaw:
+        flags |= F_POWERLAW
+    if phys.dpcap:
+        flags |= F_DPCAP
+    if k0field:
+        flags |= F_K0FIELD
+    if phys.mech_off:
+        flags |= F_MECHOFF
+    p.flags = flags
+    for name, ctype in Params._fields_:
+        if ctype is C.c_double:
+            setattr(p, name, float(getattr(phys, name)))
+    p.nup = int(phys.nup)
+    return p

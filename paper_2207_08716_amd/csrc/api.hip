@@ -1,0 +1,421 @@
+// Host side of the C ABI declared in include/ptporo.h.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "pt_internal.h"
+
+using namespace ptk;
+
+struct pt_grid {
+    Geom geom;
+    pt_params prm;
+    Coef coef;
+    double* f[PT_NFIELDS][2];
+    int cur[PT_NPING];
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    hipStream_t stream = nullptr;
+    int64_t iter = 0;          // iteration count within the current step
+    bool refreshed = false;    // any refresh done on this handle
+    bool norms_pending = false;
+    std::string err;
+};
+
+namespace {
+
+pt_status fail(pt_grid* g, pt_status s, const char* msg) {
+    if (g) g->err = msg;
+    return s;
+}
+
+pt_status hip_fail(pt_grid* g, hipError_t e, const char* where) {
+    if (g) {
+        g->err = std::string(where) + ": " + hipGetErrorString(e);
+    }
+    return PT_EDEVICE;
+}
+
+bool valid_params(const pt_params* p) {
+    if (!p || p->version != PT_ABI_VERSION) return false;
+    const double pos[] = {p->lx, p->ly, p->lz, p->phi0, p->kmuf0, p->eta0, p->mu0, p->cmu, p->alpha,
+                          p->B, p->G, p->R0, p->dt, p->dtS, p->rho_i, p->c_v, p->c_pf};
+    for (double v : pos)
+        if (!(v > 0.0) || !std::isfinite(v)) return false;
+    if (!(p->phi0 < 1.0) || p->nup < 1 || p->beta_d < 0.0 || p->beta_phi < 0.0 || p->beta_n < 0.0) return false;
+    return true;
+}
+
+void make_coef(pt_grid* g) {
+    const pt_params& p = g->prm;
+    Coef& c = g->coef;
+    const double dx = p.lx / g->geom.nx, dy = p.ly / g->geom.ny, dz = p.lz / g->geom.nz;
+    const double h = std::fmin(dx, std::fmin(dy, dz));
+    const int nmax = std::max(g->geom.nx, std::max(g->geom.ny, g->geom.nz));
+    c.dxi = 1.0 / dx;
+    c.dyi = 1.0 / dy;
+    c.dzi = 1.0 / dz;
+    c.dt = p.dt;
+    c.dti = 1.0 / p.dt;
+    c.beta_d = p.beta_d;
+    c.alpha = p.alpha;
+    c.B = p.B;
+    c.beta_phi = p.beta_phi;
+    c.rhofg = p.rhofg;
+    c.rhosg = p.rhosg;
+    c.rhobg = p.rhofg * p.phi0 + (1.0 - p.phi0) * p.rhosg;
+    c.buoy = p.rhofg - c.rhobg;
+    c.gdts_inv = 1.0 / (p.G * p.dtS);
+    c.beta_n = p.beta_n;
+    c.rho_i_inv = 1.0 / p.rho_i;
+    c.dtauv_c = p.rho_i * h * h / (p.c_v * (1.0 + p.beta_n));
+    c.dtaupt_c = (1.0 + p.beta_n) / nmax;
+    c.dtaupf_c = h * h * (1.0 + p.beta_d * p.B / p.alpha) / p.c_pf;
+    c.dampx = 1.0 - p.damp_c / g->geom.nx;
+    c.dampy = 1.0 - p.damp_c / g->geom.ny;
+    c.dampz = 1.0 - p.damp_c / g->geom.nz;
+    c.ab = p.alpha / p.B;
+    c.third = 1.0 / 3.0;
+    c.mech_off = (p.flags & PT_F_MECHOFF) ? 1 : 0;
+}
+
+RefreshCoef make_refresh(const pt_grid* g, double r_eta, double r_mu) {
+    const pt_params& p = g->prm;
+    RefreshCoef r{};
+    r.phi0 = p.phi0;
+    r.kmuf0 = p.kmuf0;
+    r.eta0 = p.eta0;
+    r.mu0 = p.mu0;
+    r.cmu = p.cmu;
+    r.R0 = p.R0;
+    r.n_pow = p.n_pow;
+    r.tau0_inv = 1.0 / p.tau0;
+    const double fr = p.fric_deg * M_PI / 180.0;
+    r.coh_cos = p.coh * std::cos(fr);
+    r.sin_f = std::sin(fr);
+    r.tau_y_min = p.tau_y_min;
+    r.r_eta = r_eta;
+    r.r_mu = r_mu;
+    r.first = g->refreshed ? 0 : 1;
+    r.powerlaw = (p.flags & PT_F_POWERLAW) ? 1 : 0;
+    r.dpcap = (p.flags & PT_F_DPCAP) ? 1 : 0;
+    r.k0field = (p.flags & PT_F_K0FIELD) ? 1 : 0;
+    return r;
+}
+
+double* cur(pt_grid* g, int f) { return f < PT_NPING ? g->f[f][g->cur[f]] : g->f[f][0]; }
+double* alt(pt_grid* g, int f) { return g->f[f][1 - g->cur[f]]; }
+
+bool bound(pt_grid* g, std::initializer_list<int> fields, bool both) {
+    for (int f : fields) {
+        if (!g->f[f][0]) return false;
+        if (both && f < PT_NPING && !g->f[f][1]) return false;
+    }
+    return true;
+}
+
+AuxPtrs aux(pt_grid* g) {
+    AuxPtrs a{};
+    a.vx = cur(g, PT_VX);
+    a.vy = cur(g, PT_VY);
+    a.vz = cur(g, PT_VZ);
+    a.pt = cur(g, PT_PT);
+    a.pf = cur(g, PT_PF);
+    a.lp = cur(g, PT_LP);
+    a.pto = cur(g, PT_PTO);
+    a.pfo = cur(g, PT_PFO);
+    a.lpo = cur(g, PT_LPO);
+    a.sxx = cur(g, PT_SXX);
+    a.syy = cur(g, PT_SYY);
+    a.szz = cur(g, PT_SZZ);
+    a.sxy = cur(g, PT_SXY);
+    a.sxz = cur(g, PT_SXZ);
+    a.syz = cur(g, PT_SYZ);
+    a.fox = cur(g, PT_FOX);
+    a.foy = cur(g, PT_FOY);
+    a.foz = cur(g, PT_FOZ);
+    a.mn = cur(g, PT_MN);
+    a.kc = cur(g, PT_KC);
+    a.eta = cur(g, PT_ETA);
+    a.mus = cur(g, PT_MUS);
+    a.k0 = g->f[PT_K0][0];
+    a.lp_o = alt(g, PT_LP);
+    return a;
+}
+
+const std::initializer_list<int> kAllCore = {PT_VX, PT_VY, PT_VZ, PT_PT, PT_PF, PT_LP, PT_RX, PT_RY,
+                                            PT_RZ, PT_PTO, PT_PFO, PT_LPO, PT_SXX, PT_SYY, PT_SZZ,
+                                            PT_SXY, PT_SXZ, PT_SYZ, PT_FOX, PT_FOY, PT_FOZ, PT_MN,
+                                            PT_KC, PT_ETA, PT_MUS};
+
+pt_status check_ready(pt_grid* g) {
+    if (!bound(g, kAllCore, true)) return fail(g, PT_EINVAL, "not every field (both copies of the iterated ones) is bound");
+    if ((g->prm.flags & PT_F_K0FIELD) && !g->f[PT_K0][0]) return fail(g, PT_EINVAL, "PT_F_K0FIELD set but PT_K0 not bound");
+    return PT_OK;
+}
+
+size_t ws_needed(const pt_grid* g) {
+    return (size_t)(iter_grid_blocks(g->geom) * NNORM + NNORM) * sizeof(double);
+}
+
+pt_status refresh_impl(pt_grid* g, double r_eta, double r_mu) {
+    const RefreshCoef r = make_refresh(g, r_eta, r_mu);
+    const AuxPtrs a = aux(g);
+    hipError_t e = launch_refresh(g->geom, g->coef, r, a, g->stream);
+    if (e != hipSuccess) return hip_fail(g, e, "refresh");
+    e = launch_fo(g->geom, g->coef, r, a, g->stream);
+    if (e != hipSuccess) return hip_fail(g, e, "fo");
+    g->refreshed = true;
+    return PT_OK;
+}
+
+pt_status iteration_impl(pt_grid* g, int update_lp, int norms) {
+    IterPtrs p{};
+    p.vx = cur(g, PT_VX); p.vy = cur(g, PT_VY); p.vz = cur(g, PT_VZ);
+    p.pt = cur(g, PT_PT); p.pf = cur(g, PT_PF); p.lp = cur(g, PT_LP);
+    p.rx = cur(g, PT_RX); p.ry = cur(g, PT_RY); p.rz = cur(g, PT_RZ);
+    p.fox = cur(g, PT_FOX); p.foy = cur(g, PT_FOY); p.foz = cur(g, PT_FOZ);
+    p.pto = cur(g, PT_PTO); p.pfo = cur(g, PT_PFO); p.lpo = cur(g, PT_LPO);
+    p.kc = cur(g, PT_KC); p.eta = cur(g, PT_ETA); p.mus = cur(g, PT_MUS);
+    p.vx_o = alt(g, PT_VX); p.vy_o = alt(g, PT_VY); p.vz_o = alt(g, PT_VZ);
+    p.pt_o = alt(g, PT_PT); p.pf_o = alt(g, PT_PF); p.lp_o = alt(g, PT_LP);
+    p.rx_o = alt(g, PT_RX); p.ry_o = alt(g, PT_RY); p.rz_o = alt(g, PT_RZ);
+    p.partials = static_cast<double*>(g->ws);
+    hipError_t e = launch_iteration(g->geom, g->coef, p, update_lp, norms, g->stream);
+    if (e != hipSuccess) return hip_fail(g, e, "iteration");
+    if (norms) {
+        const int64_t nb = iter_grid_blocks(g->geom);
+        double* out = static_cast<double*>(g->ws) + nb * NNORM;
+        e = launch_reduce_max(static_cast<double*>(g->ws), nb, out, g->stream);
+        if (e != hipSuccess) return hip_fail(g, e, "reduce");
+        g->norms_pending = true;
+    }
+    for (int f = 0; f < PT_NPING; ++f) {
+        if (f == PT_LP && !update_lp) continue;
+        g->cur[f] ^= 1;
+    }
+    g->iter += 1;
+    return PT_OK;
+}
+
+pt_status read_norms(pt_grid* g, pt_norms* out) {
+    const int64_t nb = iter_grid_blocks(g->geom);
+    double host[NNORM];
+    hipError_t e = hipMemcpyAsync(host, static_cast<double*>(g->ws) + nb * NNORM, sizeof(host),
+                                  hipMemcpyDeviceToHost, g->stream);
+    if (e != hipSuccess) return hip_fail(g, e, "norms copy");
+    e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) return hip_fail(g, e, "norms sync");
+    out->f = host[0]; out->rpt = host[1]; out->rpf = host[2]; out->dl = host[3];
+    out->dpt = host[4]; out->dpf = host[5]; out->dvz = host[6]; out->dv = host[7];
+    for (double v : host)
+        if (!std::isfinite(v)) return fail(g, PT_EDIVERGED, "non-finite residual norm");
+    return PT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t pt_abi_version(void) { return PT_ABI_VERSION; }
+
+const char* pt_status_str(pt_status s) {
+    switch (s) {
+        case PT_OK: return "ok";
+        case PT_ENOTCONV: return "iteration limit reached";
+        case PT_EINVAL: return "invalid argument";
+        case PT_EDEVICE: return "device error";
+        case PT_EDIVERGED: return "diverged (non-finite norm)";
+        case PT_EDOMAIN: return "porosity out of (0,1)";
+        case PT_ESTATE: return "handle in error state";
+    }
+    return "unknown status";
+}
+
+const char* pt_last_error(const pt_grid* g) { return g ? g->err.c_str() : "null handle"; }
+
+pt_status pt_create(int32_t nx, int32_t ny, int32_t nz, int64_t row_pitch, const pt_params* params,
+                    pt_grid** out) {
+    if (!out) return PT_EINVAL;
+    *out = nullptr;
+    if (nx < 2 || ny < 2 || nz < 2 || row_pitch < (int64_t)nx + 1) return PT_EINVAL;
+    if (!valid_params(params)) return PT_EINVAL;
+    pt_grid* g = new (std::nothrow) pt_grid();
+    if (!g) return PT_EINVAL;
+    g->geom.nx = nx;
+    g->geom.ny = ny;
+    g->geom.nz = nz;
+    g->geom.P = row_pitch;
+    g->geom.S = row_pitch * (int64_t)(ny + 1);
+    g->prm = *params;
+    std::memset(g->f, 0, sizeof(g->f));
+    std::memset(g->cur, 0, sizeof(g->cur));
+    make_coef(g);
+    *out = g;
+    return PT_OK;
+}
+
+pt_status pt_destroy(pt_grid* g) {
+    delete g;
+    return PT_OK;
+}
+
+int64_t pt_field_elems(const pt_grid* g) { return g ? g->geom.S * (int64_t)(g->geom.nz + 1) : 0; }
+
+pt_status pt_bind_field(pt_grid* g, int32_t field, int32_t copy, void* dev_ptr) {
+    if (!g) return PT_EINVAL;
+    if (field < 0 || field >= PT_NFIELDS) return fail(g, PT_EINVAL, "bad field id");
+    if (copy < 0 || copy > 1 || (copy == 1 && field >= PT_NPING)) return fail(g, PT_EINVAL, "bad copy index");
+    if (!dev_ptr || (reinterpret_cast<uintptr_t>(dev_ptr) & 255u)) return fail(g, PT_EINVAL, "null or unaligned pointer");
+    g->f[field][copy] = static_cast<double*>(dev_ptr);
+    return PT_OK;
+}
+
+pt_status pt_workspace_size(const pt_grid* g, size_t* bytes) {
+    if (!g || !bytes) return PT_EINVAL;
+    *bytes = ws_needed(g);
+    return PT_OK;
+}
+
+pt_status pt_bind_workspace(pt_grid* g, void* dev_ptr, size_t bytes) {
+    if (!g) return PT_EINVAL;
+    if (!dev_ptr || bytes < ws_needed(g)) return fail(g, PT_EINVAL, "workspace missing or too small");
+    g->ws = dev_ptr;
+    g->ws_bytes = bytes;
+    return PT_OK;
+}
+
+pt_status pt_set_stream(pt_grid* g, void* hip_stream) {
+    if (!g) return PT_EINVAL;
+    g->stream = static_cast<hipStream_t>(hip_stream);
+    return PT_OK;
+}
+
+pt_status pt_set_params(pt_grid* g, const pt_params* params) {
+    if (!g) return PT_EINVAL;
+    if (!valid_params(params)) return fail(g, PT_EINVAL, "invalid parameters");
+    g->prm = *params;
+    make_coef(g);
+    return PT_OK;
+}
+
+pt_status pt_current(const pt_grid* g, int32_t field, int32_t* copy) {
+    if (!g || !copy || field < 0 || field >= PT_NFIELDS) return PT_EINVAL;
+    *copy = field < PT_NPING ? g->cur[field] : 0;
+    return PT_OK;
+}
+
+pt_status pt_begin_step(pt_grid* g, int32_t update_history) {
+    if (!g) return PT_EINVAL;
+    pt_status st = check_ready(g);
+    if (st != PT_OK) return st;
+    const AuxPtrs a = aux(g);
+    hipError_t e = launch_begin_step(g->geom, g->coef, a, update_history, g->stream);
+    if (e != hipSuccess) return hip_fail(g, e, "begin_step");
+    if (update_history) {
+        const RefreshCoef r = make_refresh(g, 1.0, 1.0);
+        e = launch_fo(g->geom, g->coef, r, a, g->stream);
+        if (e != hipSuccess) return hip_fail(g, e, "fo");
+    }
+    g->iter = 0;
+    return PT_OK;
+}
+
+pt_status pt_refresh(pt_grid* g, double r_eta, double r_mu) {
+    if (!g) return PT_EINVAL;
+    pt_status st = check_ready(g);
+    if (st != PT_OK) return st;
+    if (!(r_eta >= 0.0 && r_eta <= 1.0 && r_mu >= 0.0 && r_mu <= 1.0)) return fail(g, PT_EINVAL, "relaxation weight outside [0,1]");
+    return refresh_impl(g, r_eta, r_mu);
+}
+
+pt_status pt_iteration(pt_grid* g, int32_t update_porosity, int32_t want_norms) {
+    if (!g) return PT_EINVAL;
+    pt_status st = check_ready(g);
+    if (st != PT_OK) return st;
+    if (want_norms && (!g->ws || g->ws_bytes < ws_needed(g))) return fail(g, PT_EINVAL, "norms need a bound workspace");
+    return iteration_impl(g, update_porosity ? 1 : 0, want_norms ? 1 : 0);
+}
+
+pt_status pt_iterate(pt_grid* g, int64_t n) {
+    if (!g || n < 0) return PT_EINVAL;
+    pt_status st = check_ready(g);
+    if (st != PT_OK) return st;
+    if (!g->ws || g->ws_bytes < ws_needed(g)) return fail(g, PT_EINVAL, "workspace not bound");
+    const int64_t nup = g->prm.nup;
+    for (int64_t m = 0; m < n; ++m) {
+        const int64_t it = g->iter + 1;
+        if ((it - 1) % nup == 0) {
+            st = refresh_impl(g, g->prm.r_eta, g->prm.r_mu);
+            if (st != PT_OK) return st;
+        }
+        st = iteration_impl(g, 1, (it % nup == 0) ? 1 : 0);
+        if (st != PT_OK) return st;
+    }
+    return PT_OK;
+}
+
+pt_status pt_last_norms(pt_grid* g, pt_norms* out) {
+    if (!g || !out) return PT_EINVAL;
+    if (!g->norms_pending) return fail(g, PT_EINVAL, "no norms computed yet");
+    return read_norms(g, out);
+}
+
+pt_status pt_solve_linear(pt_grid* g, double rtol, int64_t max_iter, int64_t* iters, double* rho) {
+    if (!g || !(rtol > 0.0) || max_iter < 1) return PT_EINVAL;
+    pt_status st = check_ready(g);
+    if (st != PT_OK) return st;
+    if (!g->ws || g->ws_bytes < ws_needed(g)) return fail(g, PT_EINVAL, "workspace not bound");
+    const int64_t nup = g->prm.nup;
+    double g0v = 0.0, g0p = 0.0, r = INFINITY;
+    int64_t it = 0;
+    while (it < max_iter) {
+        ++it;
+        const bool want = (it == 1) || (it % nup == 0);
+        st = iteration_impl(g, 0, want ? 1 : 0);
+        if (st != PT_OK) return st;
+        if (!want) continue;
+        pt_norms nm;
+        st = read_norms(g, &nm);
+        if (st != PT_OK) {
+            if (iters) *iters = it;
+            return st;
+        }
+        const double gv = nm.f, gp = std::fmax(nm.rpt, nm.rpf);
+        if (it == 1) {
+            g0v = gv;
+            g0p = gp;
+        }
+        r = 0.0;
+        if (g0v > 0.0) r = std::fmax(r, gv / g0v);
+        if (g0p > 0.0) r = std::fmax(r, gp / g0p);
+        if (it % nup == 0 && r <= rtol) break;
+    }
+    if (iters) *iters = it;
+    if (rho) *rho = r;
+    return (r <= rtol) ? PT_OK : PT_ENOTCONV;
+}
+
+pt_status pt_porosity_step(pt_grid* g) {
+    if (!g) return PT_EINVAL;
+    pt_status st = check_ready(g);
+    if (st != PT_OK) return st;
+    const AuxPtrs a = aux(g);
+    hipError_t e = launch_porosity_step(g->geom, g->coef, a, g->stream);
+    if (e != hipSuccess) return hip_fail(g, e, "porosity_step");
+    g->cur[PT_LP] ^= 1;
+    return PT_OK;
+}
+
+pt_status pt_copy(pt_grid* g, const void* src, void* dst, int64_t n) {
+    if (!g || !src || !dst || n < 0) return PT_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15u)
+        return fail(g, PT_EINVAL, "copy buffers must be 16-byte aligned");
+    hipError_t e = launch_copy(static_cast<const double*>(src), static_cast<double*>(dst), n, g->stream);
+    if (e != hipSuccess) return hip_fail(g, e, "copy");
+    return PT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,293 @@
+// Per-step and per-refresh kernels: old values and stress history, Picard
+// refresh of the lagged coefficients, the folded stress-history divergence Fo,
+// the porosity time step of a Picard stage, and a streaming copy.
+//
+// These run once per physical step or once every nup PT iterations, so they
+// are plain one-thread-per-point stencils that read neighbours through the
+// caches.
+#include "pt_internal.h"
+
+namespace ptk {
+
+namespace {
+
+constexpr int AB = 256;
+
+struct Idx {
+    int i, j, k;
+};
+
+__device__ __forceinline__ bool box_index(const Geom& g, int64_t t, Idx& q) {
+    // one thread per point of the (nx+1) x (ny+1) x (nz+1) box
+    const int64_t nxp = g.nx + 1, nyp = g.ny + 1;
+    const int64_t n = nxp * nyp * (g.nz + 1);
+    if (t >= n) return false;
+    q.i = (int)(t % nxp);
+    q.j = (int)((t / nxp) % nyp);
+    q.k = (int)(t / (nxp * nyp));
+    return true;
+}
+
+__device__ __forceinline__ int64_t at(const Geom& g, int i, int j, int k) {
+    return (int64_t)k * g.S + (int64_t)j * g.P + i;
+}
+
+// Maxwell coefficients of eq (21) (backward Euler): xi = mu/(G dtS),
+// a = xi/(1+xi) multiplies the stress history, b = 2 mu/(1+xi) the strain rate.
+__device__ __forceinline__ double coef_a(double mu, double gdts_inv) {
+    const double xi = mu * gdts_inv;
+    return xi / (1.0 + xi);
+}
+__device__ __forceinline__ double coef_b(double mu, double gdts_inv) {
+    const double xi = mu * gdts_inv;
+    return 2.0 * mu / (1.0 + xi);
+}
+
+// Deviatoric stresses at the current state without the numerical
+// compressibility term: tau = a * So + b * edot.  Boundary edges carry zero.
+struct StressEval {
+    const Geom& g;
+    const Coef& c;
+    const AuxPtrs& a;
+    __device__ double mus(int i, int j, int k) const { return a.mus[at(g, i, j, k)]; }
+    __device__ double divv(int i, int j, int k) const {
+        return (a.vx[at(g, i + 1, j, k)] - a.vx[at(g, i, j, k)]) * c.dxi +
+               (a.vy[at(g, i, j + 1, k)] - a.vy[at(g, i, j, k)]) * c.dyi +
+               (a.vz[at(g, i, j, k + 1)] - a.vz[at(g, i, j, k)]) * c.dzi;
+    }
+    __device__ void normal(int i, int j, int k, double& txx, double& tyy, double& tzz) const {
+        const int64_t o = at(g, i, j, k);
+        const double mu = a.mus[o];
+        const double aa = coef_a(mu, c.gdts_inv), bb = coef_b(mu, c.gdts_inv);
+        const double dxv = (a.vx[at(g, i + 1, j, k)] - a.vx[o]) * c.dxi;
+        const double dyv = (a.vy[at(g, i, j + 1, k)] - a.vy[o]) * c.dyi;
+        const double dzv = (a.vz[at(g, i, j, k + 1)] - a.vz[o]) * c.dzi;
+        const double d3 = (dxv + dyv + dzv) * c.third;
+        txx = aa * a.sxx[o] + bb * (dxv - d3);
+        tyy = aa * a.syy[o] + bb * (dyv - d3);
+        tzz = aa * a.szz[o] + bb * (dzv - d3);
+    }
+    __device__ double xy(int i, int j, int k) const {
+        if (i < 1 || i >= g.nx || j < 1 || j >= g.ny) return 0.0;
+        const double mue = 0.25 * (mus(i - 1, j - 1, k) + mus(i, j - 1, k) + mus(i - 1, j, k) + mus(i, j, k));
+        const int64_t o = at(g, i, j, k);
+        const double e = 0.5 * ((a.vx[o] - a.vx[at(g, i, j - 1, k)]) * c.dyi + (a.vy[o] - a.vy[at(g, i - 1, j, k)]) * c.dxi);
+        return coef_a(mue, c.gdts_inv) * a.sxy[o] + coef_b(mue, c.gdts_inv) * e;
+    }
+    __device__ double xz(int i, int j, int k) const {
+        if (i < 1 || i >= g.nx || k < 1 || k >= g.nz) return 0.0;
+        const double mue = 0.25 * (mus(i - 1, j, k - 1) + mus(i, j, k - 1) + mus(i - 1, j, k) + mus(i, j, k));
+        const int64_t o = at(g, i, j, k);
+        const double e = 0.5 * ((a.vx[o] - a.vx[at(g, i, j, k - 1)]) * c.dzi + (a.vz[o] - a.vz[at(g, i - 1, j, k)]) * c.dxi);
+        return coef_a(mue, c.gdts_inv) * a.sxz[o] + coef_b(mue, c.gdts_inv) * e;
+    }
+    __device__ double yz(int i, int j, int k) const {
+        if (j < 1 || j >= g.ny || k < 1 || k >= g.nz) return 0.0;
+        const double mue = 0.25 * (mus(i, j - 1, k - 1) + mus(i, j, k - 1) + mus(i, j - 1, k) + mus(i, j, k));
+        const int64_t o = at(g, i, j, k);
+        const double e = 0.5 * ((a.vy[o] - a.vy[at(g, i, j, k - 1)]) * c.dzi + (a.vz[o] - a.vz[at(g, i, j - 1, k)]) * c.dyi);
+        return coef_a(mue, c.gdts_inv) * a.syz[o] + coef_b(mue, c.gdts_inv) * e;
+    }
+};
+
+// Start of a physical step: old pressures and porosity; optionally the new
+// stress history (computed into registers first, written after a grid-wide
+// separation: the history write happens in a second kernel).
+__global__ __launch_bounds__(AB) void k_old_values(Geom g, AuxPtrs a) {
+    Idx q;
+    if (!box_index(g, (int64_t)blockIdx.x * AB + threadIdx.x, q)) return;
+    if (q.i >= g.nx || q.j >= g.ny || q.k >= g.nz) return;
+    const int64_t o = at(g, q.i, q.j, q.k);
+    a.pto[o] = a.pt[o];
+    a.pfo[o] = a.pf[o];
+    a.lpo[o] = a.lp[o];
+}
+
+// Stress history <- tau(present state).  Each point reads only its own
+// history value and the (read-only) velocities and viscosities, so the
+// update can be done in place.
+__global__ __launch_bounds__(AB) void k_history(Geom g, Coef c, AuxPtrs a) {
+    Idx q;
+    if (!box_index(g, (int64_t)blockIdx.x * AB + threadIdx.x, q)) return;
+    const StressEval se{g, c, a};
+    const int i = q.i, j = q.j, k = q.k;
+    const int64_t o = at(g, i, j, k);
+    if (i < g.nx && j < g.ny && k < g.nz) {
+        double txx, tyy, tzz;
+        se.normal(i, j, k, txx, tyy, tzz);
+        a.sxx[o] = txx;
+        a.syy[o] = tyy;
+        a.szz[o] = tzz;
+    }
+    if (k < g.nz) a.sxy[o] = se.xy(i, j, k);
+    if (j < g.ny) a.sxz[o] = se.xz(i, j, k);
+    if (i < g.nx) a.syz[o] = se.yz(i, j, k);
+}
+
+// Picard refresh (eqs (23)-(26)) of k/mu_f, eta_phi and Mn at the cells.
+// mu_s itself is rewritten by k_fo (other cells still read it here).
+__global__ __launch_bounds__(AB) void k_refresh(Geom g, Coef c, RefreshCoef r, AuxPtrs a) {
+    Idx q;
+    if (!box_index(g, (int64_t)blockIdx.x * AB + threadIdx.x, q)) return;
+    const int i = q.i, j = q.j, k = q.k;
+    if (i >= g.nx || j >= g.ny || k >= g.nz) return;
+    const int64_t o = at(g, i, j, k);
+    const double s = exp(a.lp[o]);
+    const double phi = 1.0 - s;
+    const double rr = phi / r.phi0;
+    const double k0 = r.k0field ? a.k0[o] : r.kmuf0;
+    const double kc = k0 * rr * rr * rr;
+
+    const double pt = a.pt[o], pf = a.pf[o], mn = a.mn[o];
+    const double R = (pf > pt) ? 1.0 / r.R0 : 1.0;
+    const double eta_new = r.eta0 * mn * (r.phi0 / phi) * R;
+    const double eta = r.first ? eta_new : exp(r.r_eta * log(eta_new) + (1.0 - r.r_eta) * log(a.eta[o]));
+
+    double mn_new = r.mu0;
+    if (r.powerlaw || r.dpcap) {
+        const StressEval se{g, c, a};
+        double txx, tyy, tzz;
+        se.normal(i, j, k, txx, tyy, tzz);
+        const double axy = 0.25 * (se.xy(i, j, k) + se.xy(i + 1, j, k) + se.xy(i, j + 1, k) + se.xy(i + 1, j + 1, k));
+        const double axz = 0.25 * (se.xz(i, j, k) + se.xz(i + 1, j, k) + se.xz(i, j, k + 1) + se.xz(i + 1, j, k + 1));
+        const double ayz = 0.25 * (se.yz(i, j, k) + se.yz(i, j + 1, k) + se.yz(i, j, k + 1) + se.yz(i, j + 1, k + 1));
+        const double tii = sqrt(0.5 * (txx * txx + tyy * tyy + tzz * tzz) + axy * axy + axz * axz + ayz * ayz);
+        if (r.powerlaw) {
+            const double t = tii * r.tau0_inv;
+            const double tp = (r.n_pow == 3.0) ? t * t : pow(t, r.n_pow - 1.0);
+            mn_new = r.mu0 / (1.0 + tp);
+        }
+        if (r.dpcap) {
+            const double ty = fmax(r.coh_cos + (pt - pf) * r.sin_f, r.tau_y_min);
+            if (tii > ty) mn_new = fmin(mn_new, mn * ty / tii);
+        }
+    }
+    const double mnr = r.first ? mn_new : exp(r.r_mu * log(mn_new) + (1.0 - r.r_mu) * log(mn));
+    a.kc[o] = kc;
+    a.eta[o] = eta;
+    a.mn[o] = mnr;
+}
+
+// mu_s = Mn phi0 cmu at the cells, and the stress-history part of the
+// momentum balance folded into face fields:
+//   Fo = div(a So) on interior faces (zero on boundary faces).
+__global__ __launch_bounds__(AB) void k_fo(Geom g, Coef c, RefreshCoef r, AuxPtrs a) {
+    Idx q;
+    if (!box_index(g, (int64_t)blockIdx.x * AB + threadIdx.x, q)) return;
+    const int i = q.i, j = q.j, k = q.k;
+    const int64_t o = at(g, i, j, k);
+    auto mus = [&](int ii, int jj, int kk) { return a.mn[at(g, ii, jj, kk)] * r.phi0 * r.cmu; };
+    auto acell = [&](int ii, int jj, int kk) { return coef_a(mus(ii, jj, kk), c.gdts_inv); };
+    auto axy = [&](int ii, int jj, int kk) -> double {
+        if (ii < 1 || ii >= g.nx || jj < 1 || jj >= g.ny) return 0.0;
+        const double mue = 0.25 * (mus(ii - 1, jj - 1, kk) + mus(ii, jj - 1, kk) + mus(ii - 1, jj, kk) + mus(ii, jj, kk));
+        return coef_a(mue, c.gdts_inv) * a.sxy[at(g, ii, jj, kk)];
+    };
+    auto axz = [&](int ii, int jj, int kk) -> double {
+        if (ii < 1 || ii >= g.nx || kk < 1 || kk >= g.nz) return 0.0;
+        const double mue = 0.25 * (mus(ii - 1, jj, kk - 1) + mus(ii, jj, kk - 1) + mus(ii - 1, jj, kk) + mus(ii, jj, kk));
+        return coef_a(mue, c.gdts_inv) * a.sxz[at(g, ii, jj, kk)];
+    };
+    auto ayz = [&](int ii, int jj, int kk) -> double {
+        if (jj < 1 || jj >= g.ny || kk < 1 || kk >= g.nz) return 0.0;
+        const double mue = 0.25 * (mus(ii, jj - 1, kk - 1) + mus(ii, jj, kk - 1) + mus(ii, jj - 1, kk) + mus(ii, jj, kk));
+        return coef_a(mue, c.gdts_inv) * a.syz[at(g, ii, jj, kk)];
+    };
+    if (i < g.nx && j < g.ny && k < g.nz) a.mus[o] = mus(i, j, k);
+    if (j < g.ny && k < g.nz) {  // x-face
+        double f = 0.0;
+        if (i >= 1 && i < g.nx)
+            f = (acell(i, j, k) * a.sxx[o] - acell(i - 1, j, k) * a.sxx[at(g, i - 1, j, k)]) * c.dxi +
+                (axy(i, j + 1, k) - axy(i, j, k)) * c.dyi + (axz(i, j, k + 1) - axz(i, j, k)) * c.dzi;
+        a.fox[o] = f;
+    }
+    if (i < g.nx && k < g.nz) {  // y-face
+        double f = 0.0;
+        if (j >= 1 && j < g.ny)
+            f = (axy(i + 1, j, k) - axy(i, j, k)) * c.dxi +
+                (acell(i, j, k) * a.syy[o] - acell(i, j - 1, k) * a.syy[at(g, i, j - 1, k)]) * c.dyi +
+                (ayz(i, j, k + 1) - ayz(i, j, k)) * c.dzi;
+        a.foy[o] = f;
+    }
+    if (i < g.nx && j < g.ny) {  // z-face
+        double f = 0.0;
+        if (k >= 1 && k < g.nz)
+            f = (axz(i + 1, j, k) - axz(i, j, k)) * c.dxi + (ayz(i, j + 1, k) - ayz(i, j, k)) * c.dyi +
+                (acell(i, j, k) * a.szz[o] - acell(i, j, k - 1) * a.szz[at(g, i, j, k - 1)]) * c.dzi;
+        a.foz[o] = f;
+    }
+}
+
+// Porosity time step of a Picard stage (eq (22)):
+//   ln(1-phi) = ln(1-phi)o - dt [beta_phi((Pf-Pfo) - (Pt-Pto))/dt + (Pf-Pt)/eta + V.grad(1-phi)]
+__global__ __launch_bounds__(AB) void k_porosity(Geom g, Coef c, AuxPtrs a) {
+    Idx q;
+    if (!box_index(g, (int64_t)blockIdx.x * AB + threadIdx.x, q)) return;
+    const int i = q.i, j = q.j, k = q.k;
+    if (i >= g.nx || j >= g.ny || k >= g.nz) return;
+    const int64_t o = at(g, i, j, k);
+    auto sf = [&](int ii, int jj, int kk) { return exp(a.lp[at(g, ii, jj, kk)]); };
+    const double s = sf(i, j, k);
+    double adv = 0.0;
+    if (i > 0) adv += 0.5 * a.vx[o] * (s - sf(i - 1, j, k)) * c.dxi;
+    if (i < g.nx - 1) adv += 0.5 * a.vx[at(g, i + 1, j, k)] * (sf(i + 1, j, k) - s) * c.dxi;
+    if (j > 0) adv += 0.5 * a.vy[o] * (s - sf(i, j - 1, k)) * c.dyi;
+    if (j < g.ny - 1) adv += 0.5 * a.vy[at(g, i, j + 1, k)] * (sf(i, j + 1, k) - s) * c.dyi;
+    if (k > 0) adv += 0.5 * a.vz[o] * (s - sf(i, j, k - 1)) * c.dzi;
+    if (k < g.nz - 1) adv += 0.5 * a.vz[at(g, i, j, k + 1)] * (sf(i, j, k + 1) - s) * c.dzi;
+    const double pt = a.pt[o], pf = a.pf[o];
+    const double dphidt = c.beta_phi * ((pf - a.pfo[o]) - (pt - a.pto[o])) * c.dti + (pf - pt) / a.eta[o] + adv;
+    a.lp_o[o] = a.lpo[o] - c.dt * dphidt;
+}
+
+__global__ __launch_bounds__(AB) void k_copy(const double2* __restrict__ src, double2* __restrict__ dst, int64_t n2) {
+    const int64_t stride = (int64_t)gridDim.x * AB;
+    for (int64_t t = (int64_t)blockIdx.x * AB + threadIdx.x; t < n2; t += stride) dst[t] = src[t];
+}
+
+__global__ void k_copy_tail(const double* __restrict__ src, double* __restrict__ dst, int64_t n) {
+    if (threadIdx.x == 0 && n % 2 == 1) dst[n - 1] = src[n - 1];
+}
+
+inline dim3 box_grid(const Geom& g) {
+    const int64_t n = (int64_t)(g.nx + 1) * (g.ny + 1) * (g.nz + 1);
+    return dim3((unsigned)((n + AB - 1) / AB));
+}
+
+}  // namespace
+
+hipError_t launch_begin_step(const Geom& g, const Coef& c, const AuxPtrs& a, int update_history,
+                             hipStream_t s) {
+    if (update_history) hipLaunchKernelGGL(k_history, box_grid(g), dim3(AB), 0, s, g, c, a);
+    hipLaunchKernelGGL(k_old_values, box_grid(g), dim3(AB), 0, s, g, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_refresh(const Geom& g, const Coef& c, const RefreshCoef& r, const AuxPtrs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_refresh, box_grid(g), dim3(AB), 0, s, g, c, r, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fo(const Geom& g, const Coef& c, const RefreshCoef& r, const AuxPtrs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_fo, box_grid(g), dim3(AB), 0, s, g, c, r, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_porosity_step(const Geom& g, const Coef& c, const AuxPtrs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_porosity, box_grid(g), dim3(AB), 0, s, g, c, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy(const double* src, double* dst, int64_t n, hipStream_t s) {
+    const int64_t n2 = n / 2;
+    if (n2 > 0) {
+        int64_t blocks = (n2 + AB - 1) / AB;
+        if (blocks > 256 * 64) blocks = 256 * 64;
+        hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(AB), 0, s,
+                           reinterpret_cast<const double2*>(src), reinterpret_cast<double2*>(dst), n2);
+    }
+    if (n % 2 == 1) hipLaunchKernelGGL(k_copy_tail, dim3(1), dim3(64), 0, s, src, dst, n);
+    return hipGetLastError();
+}
+
+}  // namespace ptk

@@ -1,0 +1,180 @@
+"""Python handle over the HIP solver: torch owns the device buffers and the
+stream, the C library (libptporo.so) does every step of the computation.
+
+Methods map one-to-one onto the C entry points; this module only allocates
+buffers, passes pointers and converts fields between the padded device layout
+and compact (z, y, x) numpy arrays for inspection.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import abi
+
+
+def field_extent(name, nx, ny, nz):
+    """(z, y, x) extent of a field inside its padded box."""
+    if name in ("vx", "rx", "fox"):
+        return (nz, ny, nx + 1)
+    if name in ("vy", "ry", "foy"):
+        return (nz, ny + 1, nx)
+    if name in ("vz", "rz", "foz"):
+        return (nz + 1, ny, nx)
+    if name == "sxy":
+        return (nz, ny + 1, nx + 1)
+    if name == "sxz":
+        return (nz + 1, ny, nx + 1)
+    if name == "syz":
+        return (nz + 1, ny + 1, nx)
+    return (nz, ny, nx)
+
+
+def _check(lib, h, st, what):
+    if st < 0:
+        msg = lib.pt_last_error(h).decode() if h else ""
+        raise abi.PTError(st, f"{what}: {msg}")
+    return st
+
+
+class Grid:
+    """Solver state on one GPU for an nx x ny x nz cell grid.
+
+    phys: paper_2207_08716_amd.inputs.Physics.  k0field: bind a per-cell
+    k0/mu_f field.  The row pitch is padded to a multiple of 32 elements.
+    """
+
+    def __init__(self, phys, nx, ny, nz, k0field=False, device="cuda", pitch=None, stream=None):
+        self.lib = abi.load()
+        self.phys = phys
+        self.nx, self.ny, self.nz = nx, ny, nz
+        self.device = torch.device(device)
+        if self.device.type != "cuda":
+            raise ValueError("the solver runs on the GPU only")
+        self.pitch = pitch or ((nx + 1 + 31) // 32) * 32
+        self.k0field = bool(k0field)
+        h = C.c_void_p()
+        self._params = abi.params_from(phys, self.k0field)
+        st = self.lib.pt_create(nx, ny, nz, self.pitch, C.byref(self._params), C.byref(h))
+        if st != 0:
+            raise abi.PTError(st, "pt_create rejected the grid or parameters")
+        self.h = h
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        _check(self.lib, h, self.lib.pt_set_stream(h, C.c_void_p(self.stream.cuda_stream)), "set_stream")
+        box = (nz + 1, ny + 1, self.pitch)
+        assert self.lib.pt_field_elems(h) == box[0] * box[1] * box[2]
+        self.buf = {}
+        with torch.cuda.stream(self.stream):
+            for fid, name in enumerate(abi.FIELDS):
+                if name == "k0" and not self.k0field:
+                    continue
+                ncopy = 2 if fid < abi.NPING else 1
+                self.buf[name] = []
+                for cp in range(ncopy):
+                    t = torch.zeros(box, dtype=torch.float64, device=self.device)
+                    self.buf[name].append(t)
+                    _check(self.lib, h, self.lib.pt_bind_field(h, fid, cp, C.c_void_p(t.data_ptr())), f"bind {name}")
+            nbytes = C.c_size_t()
+            _check(self.lib, h, self.lib.pt_workspace_size(h, C.byref(nbytes)), "workspace_size")
+            self.ws = torch.zeros((nbytes.value + 7) // 8, dtype=torch.float64, device=self.device)
+            _check(self.lib, h, self.lib.pt_bind_workspace(h, C.c_void_p(self.ws.data_ptr()), nbytes.value), "bind ws")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.pt_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- state access --------------------------------------------------------
+    def tensor(self, name):
+        """Device tensor (padded box) holding the present value of a field."""
+        fid = abi.FIELD_ID[name]
+        cp = C.c_int32()
+        _check(self.lib, self.h, self.lib.pt_current(self.h, fid, C.byref(cp)), "current")
+        return self.buf[name][cp.value]
+
+    def view(self, name):
+        """Device view of the field's extent inside its padded box."""
+        ez, ey, ex = field_extent(name, self.nx, self.ny, self.nz)
+        return self.tensor(name)[:ez, :ey, :ex]
+
+    def get(self, name) -> np.ndarray:
+        with torch.cuda.stream(self.stream):
+            out = self.view(name).cpu().numpy().copy()
+        return out
+
+    def set(self, name, value):
+        """Write a field (numpy array of the field's extent, or a scalar) into
+        the present copy."""
+        with torch.cuda.stream(self.stream):
+            v = self.view(name)
+            if np.isscalar(value):
+                v.fill_(float(value))
+            else:
+                a = np.ascontiguousarray(value, dtype=np.float64)
+                assert a.shape == tuple(v.shape), (name, a.shape, tuple(v.shape))
+                v.copy_(torch.from_numpy(a).to(self.device, non_blocking=False))
+
+    def load_initial(self, phi, k0=None):
+        """Initial state of every workload: V = R = 0, pressures 0, stress
+        history 0, ln(1-phi) from phi, Mn = mu0; coefficients take their
+        background values until the first refresh."""
+        ph = self.phys
+        lp = np.log(1.0 - np.asarray(phi, dtype=np.float64))
+        self.set("lp", lp)
+        self.set("lpo", lp)
+        self.set("mn", ph.mu0)
+        self.set("eta", 1.0)
+        self.set("mus", ph.mu0 * ph.phi0 * ph.cmu)
+        self.set("kc", ph.kmuf0)
+        if self.k0field:
+            if k0 is None:
+                raise ValueError("k0 field expected")
+            self.set("k0", k0)
+        elif k0 is not None:
+            raise ValueError("grid created without a k0 field")
+
+    # ---- solver entry points --------------------------------------------------
+    def begin_step(self, update_history=False):
+        _check(self.lib, self.h, self.lib.pt_begin_step(self.h, int(bool(update_history))), "begin_step")
+
+    def refresh(self, r_eta=None, r_mu=None):
+        r_eta = self.phys.r_eta if r_eta is None else r_eta
+        r_mu = self.phys.r_mu if r_mu is None else r_mu
+        _check(self.lib, self.h, self.lib.pt_refresh(self.h, float(r_eta), float(r_mu)), "refresh")
+
+    def iteration(self, update_lp=True, norms=False):
+        _check(self.lib, self.h, self.lib.pt_iteration(self.h, int(bool(update_lp)), int(bool(norms))), "iteration")
+
+    def iterate(self, n):
+        _check(self.lib, self.h, self.lib.pt_iterate(self.h, int(n)), "iterate")
+
+    def last_norms(self) -> dict:
+        nm = abi.Norms()
+        _check(self.lib, self.h, self.lib.pt_last_norms(self.h, C.byref(nm)), "last_norms")
+        return {n: getattr(nm, n) for n, _ in abi.Norms._fields_}
+
+    def solve_linear(self, rtol, max_iter=1_000_000):
+        it = C.c_int64()
+        rho = C.c_double()
+        st = _check(self.lib, self.h, self.lib.pt_solve_linear(self.h, float(rtol), int(max_iter),
+                                                                 C.byref(it), C.byref(rho)), "solve_linear")
+        return it.value, rho.value, st == 0
+
+    def porosity_step(self):
+        _check(self.lib, self.h, self.lib.pt_porosity_step(self.h), "porosity_step")
+
+    def copy(self, src: torch.Tensor, dst: torch.Tensor):
+        assert src.dtype == dst.dtype == torch.float64 and src.numel() == dst.numel()
+        _check(self.lib, self.h, self.lib.pt_copy(self.h, C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()),
+                                                  src.numel()), "copy")
+
+    def synchronize(self):
+        self.stream.synchronize()

@@ -1,0 +1,196 @@
+"""GPU (HIP, through the C ABI) against the FP64 oracle, element by element.
+
+Tolerance: relative infinity norm per field, ||gpu - oracle|| / ||oracle||,
+at most 1e-12 for FP64 after a fixed number of iterations.  The two sides
+round differently (fused multiply-adds, reciprocals instead of divisions, the
+stress history folded into face fields), so bitwise equality is not expected;
+the PT iteration damps these rounding differences.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2207_08716_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+STATE = ("vx", "vy", "vz", "pt", "pf", "lp", "rx", "ry", "rz")
+COEF = ("kc", "eta", "mus", "mn")
+
+
+def _rel(a, b):
+    s = np.abs(b).max()
+    d = np.abs(a - b).max()
+    return d / s if s > 0 else d
+
+
+def _pair(cfg):
+    from paper_2207_08716_amd import schedules
+    f = inputs.initial_fields(cfg)
+    g = schedules.make_grid(cfg, f)
+    o = oracle.Oracle(cfg.phys, cfg.nx, cfg.ny, cfg.nz, f["phi"], f["k0"])
+    return g, o
+
+
+def _r_scale(o):
+    """Scale of the damped momentum residual R = f/rho_i + d R.  f is the
+    small difference of the stress divergence and the pressure gradient, so
+    its rounding error is relative to those terms, not to f: bound it by the
+    pressure-gradient magnitude max|Pt|/h summed over the damping memory
+    1/(1-d)."""
+    ph = o.phys
+    h = min(ph.lx / o.nx, ph.ly / o.ny, ph.lz / o.nz)
+    n = max(o.nx, o.ny, o.nz)
+    grad = max(np.abs(o.f["pt"]).max(), np.abs(o.f["pf"]).max(), 1e-300) / h
+    return grad * n / ph.damp_c / ph.rho_i
+
+
+def _compare(g, o, names=STATE + COEF, tol=TOL):
+    worst = {}
+    for n in names:
+        if n in ("rx", "ry", "rz"):
+            worst[n] = np.abs(g.get(n) - o.f[n]).max() / max(_r_scale(o), np.abs(o.f[n]).max())
+        else:
+            worst[n] = _rel(g.get(n), o.f[n])
+    print({k: f"{v:.2e}" for k, v in worst.items()}, flush=True)
+    bad = {k: v for k, v in worst.items() if not v <= tol}
+    assert not bad, bad
+
+
+def test_parity_thesis_schedule_32_cubed_1000_iterations():
+    """The FP64 parity workload: 32^3, one anomaly, noise, 1000 iterations."""
+    cfg = inputs.config_parity(32)
+    g, o = _pair(cfg)
+    g.begin_step(False)
+    g.iterate(1000)
+    o.begin_step()
+    o.iterate(1000)
+    _compare(g, o)
+    ng = g.last_norms()
+    no = o.history[-1]
+    for k_g, k_o in (("f", "f"), ("rpt", "rpt"), ("rpf", "rpf"), ("dl", "dL"), ("dpt", "dPt"),
+                     ("dpf", "dPf"), ("dvz", "dVz"), ("dv", "dV")):
+        assert abs(ng[k_g] - no[k_o]) <= 1e-7 * abs(no[k_o]) + 1e-15, (k_g, ng[k_g], no[k_o])
+
+
+@pytest.mark.parametrize("shape", [(70, 13, 130), (125, 9, 66), (2, 2, 2), (3, 64, 5)])
+def test_parity_ragged_tiles_power_law_cap_k0(shape):
+    """Several x/y tiles and z chunks with ragged tails; heterogeneous k0,
+    power-law viscosity and a yield cap (friction angle 0) that yields."""
+    nx, ny, nz = shape
+    cfg = inputs.config_fp64_picard(8)
+    cfg = cfg.__class__(**{**cfg.__dict__, "nx": nx, "ny": ny, "nz": nz, "name": f"ragged{shape}"})
+    cfg.phys = cfg.phys.replace(powerlaw=True, dpcap=True, coh=2e-3, fric_deg=0.0, tau_y_min=1e-6,
+                                lx=nx / 40, ly=ny / 40, lz=nz / 40)
+    g, o = _pair(cfg)
+    g.begin_step(False)
+    g.iterate(95)
+    o.begin_step()
+    o.iterate(95)
+    _compare(g, o)
+
+
+def test_parity_drucker_prager_friction():
+    """Cap with friction: tau_y = C cos(f) + (Pt - Pf) sin(f).  The cohesion
+    keeps tau_y well away from zero (where the yield stress is a small
+    difference of large terms and amplifies pressure rounding)."""
+    cfg = inputs.config_parity(24)
+    cfg.phys = cfg.phys.replace(dpcap=True, coh=0.02, fric_deg=30.0, tau_y_min=1e-3)
+    g, o = _pair(cfg)
+    g.begin_step(False)
+    g.iterate(120)
+    o.begin_step()
+    o.iterate(120)
+    _compare(g, o)
+    assert (o.f["mn"] < cfg.phys.mu0).mean() > 0.01   # the cap engaged somewhere
+
+
+def test_parity_two_steps_with_stress_history():
+    """Second physical step: stress history from the first step's state,
+    folded into face fields on the GPU and used directly by the oracle."""
+    cfg = inputs.config_parity(20)
+    cfg.phys = cfg.phys.replace(dtS=2e-5, powerlaw=True)
+    g, o = _pair(cfg)
+    for step in range(3):
+        g.begin_step(step >= 1)
+        g.iterate(60)
+        o.begin_step()
+        o.iterate(60)
+        o.end_step()
+    _compare(g, o)
+    _compare(g, o, names=("sxx", "syy", "szz", "sxy", "sxz", "syz", "pto", "pfo", "lpo"))
+
+
+def test_parity_picard_stages():
+    """Picard schedule primitives: refresh without relaxation, linear
+    iterations with porosity frozen, porosity time step."""
+    cfg = inputs.config_fp64_picard(24)
+    g, o = _pair(cfg)
+    g.begin_step(False)
+    o.begin_step()
+    for n in (300, 150):
+        g.refresh(1.0, 1.0)
+        o.refresh(1.0, 1.0)
+        for it in range(n):
+            g.iteration(update_lp=False, norms=(it == n - 1))
+            o.iteration(update_lp=False)
+        g.porosity_step()
+        o.porosity_step()
+    _compare(g, o)
+
+
+def test_solve_linear_matches_oracle():
+    cfg = inputs.config_fp64_picard(16)
+    cfg.phys = cfg.phys.replace(dt=1e-5, dtS=1e-5)
+    g, o = _pair(cfg)
+    g.begin_step(False)
+    o.begin_step()
+    g.refresh(1.0, 1.0)
+    o.refresh(1.0, 1.0)
+    it_g, rho_g, ok = g.solve_linear(1e-6, 20000)
+    it_o, rho_o = o.solve_linear(1e-6, 20000)
+    print("gpu", it_g, rho_g, "oracle", it_o, rho_o)
+    assert ok and rho_g <= 1e-6
+    assert abs(it_g - it_o) <= cfg.phys.nup
+    if it_g == it_o:
+        _compare(g, o, names=STATE, tol=1e-10)
+
+
+def test_bitwise_deterministic():
+    cfg = inputs.config_fp64_picard(20)
+    runs = []
+    for _ in range(2):
+        g, _o = _pair(cfg)
+        g.begin_step(False)
+        g.iterate(40)
+        runs.append({n: g.get(n) for n in STATE})
+    for n in STATE:
+        assert np.array_equal(runs[0][n], runs[1][n]), n
+
+
+def test_norms_flag_divergence():
+    """A non-finite state is reported as PT_EDIVERGED by the norm read."""
+    from paper_2207_08716_amd import abi
+    cfg = inputs.config_parity(8)
+    g, _o = _pair(cfg)
+    g.begin_step(False)
+    g.refresh()
+    pf = g.get("pf")
+    pf[3, 3, 3] = np.nan
+    g.set("pf", pf)
+    g.iteration(update_lp=True, norms=True)
+    with pytest.raises(abi.PTError) as e:
+        g.last_norms()
+    assert e.value.status == -3
+
+
+def test_copy_kernel():
+    import torch
+    cfg = inputs.config_parity(8)
+    g, _o = _pair(cfg)
+    src = torch.randn(1_000_003, dtype=torch.float64, device="cuda")
+    dst = torch.zeros_like(src)
+    g.copy(src, dst)
+    torch.cuda.synchronize()
+    assert torch.equal(src, dst)
