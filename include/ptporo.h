@@ -25,8 +25,9 @@
  *   pt_field_elems() doubles.  Cells use i < nx, j < ny, k < nz; x-faces
  *   i <= nx; y-faces j <= ny; z-faces k <= nz; xy-edges i <= nx, j <= ny;
  *   xz-edges i <= nx, k <= nz; yz-edges j <= ny, k <= nz.  Entries outside a
- *   field's extent are never read or written.  Base pointers must be 256-byte
- *   aligned; row_pitch >= nx + 1.
+ *   field's extent are never written; the kernels may read them (every load
+ *   stays inside the buffer) and ignore their values.  Base pointers must be
+ *   256-byte aligned; row_pitch >= nx + 1.
  * State.  The nine iterated fields (PT_VX .. PT_RZ) are double-buffered
  *   (Jacobi iteration: no point reads a value written in the same sweep).
  *   Bind both copies (copy 0 and 1); pt_current() tells which copy holds the

@@ -240,9 +240,25 @@ __global__ __launch_bounds__(AB) void k_porosity(Geom g, Coef c, AuxPtrs a) {
     a.lp_o[o] = a.lpo[o] - c.dt * dphidt;
 }
 
-__global__ __launch_bounds__(AB) void k_copy(const double2* __restrict__ src, double2* __restrict__ dst, int64_t n2) {
-    const int64_t stride = (int64_t)gridDim.x * AB;
-    for (int64_t t = (int64_t)blockIdx.x * AB + threadIdx.x; t < n2; t += stride) dst[t] = src[t];
+// Streaming copy: each thread moves CU_UNROLL 16-byte vectors per pass, all
+// loads issued before the stores.
+constexpr int CU_UNROLL = 4;
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+__global__ __launch_bounds__(AB) void k_copy(const dvec2* __restrict__ src, dvec2* __restrict__ dst, int64_t n2) {
+    const int64_t chunk = (int64_t)AB * CU_UNROLL;
+    for (int64_t base = (int64_t)blockIdx.x * chunk; base < n2; base += (int64_t)gridDim.x * chunk) {
+        dvec2 v[CU_UNROLL];
+#pragma unroll
+        for (int u = 0; u < CU_UNROLL; ++u) {
+            const int64_t t = base + u * AB + threadIdx.x;
+            if (t < n2) v[u] = __builtin_nontemporal_load(src + t);
+        }
+#pragma unroll
+        for (int u = 0; u < CU_UNROLL; ++u) {
+            const int64_t t = base + u * AB + threadIdx.x;
+            if (t < n2) __builtin_nontemporal_store(v[u], dst + t);
+        }
+    }
 }
 
 __global__ void k_copy_tail(const double* __restrict__ src, double* __restrict__ dst, int64_t n) {
@@ -281,10 +297,10 @@ hipError_t launch_porosity_step(const Geom& g, const Coef& c, const AuxPtrs& a, 
 hipError_t launch_copy(const double* src, double* dst, int64_t n, hipStream_t s) {
     const int64_t n2 = n / 2;
     if (n2 > 0) {
-        int64_t blocks = (n2 + AB - 1) / AB;
-        if (blocks > 256 * 64) blocks = 256 * 64;
+        int64_t blocks = (n2 + (int64_t)AB * CU_UNROLL - 1) / ((int64_t)AB * CU_UNROLL);
+        if (blocks > 256 * 32) blocks = 256 * 32;
         hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(AB), 0, s,
-                           reinterpret_cast<const double2*>(src), reinterpret_cast<double2*>(dst), n2);
+                           reinterpret_cast<const dvec2*>(src), reinterpret_cast<dvec2*>(dst), n2);
     }
     if (n % 2 == 1) hipLaunchKernelGGL(k_copy_tail, dim3(1), dim3(64), 0, s, src, dst, n);
     return hipGetLastError();

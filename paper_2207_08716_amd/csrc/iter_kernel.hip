@@ -72,10 +72,40 @@ __global__ __launch_bounds__(BX * BY) void k_iter(Geom g, Coef c, IterPtrs p) {
     const bool outc = cell && tx >= 1 && tx <= BX - 2 && ty >= 1 && ty <= BY - 2;
     const bool cellq = cell && tx <= BX - 2 && ty <= BY - 2;
     const bool edge = tx >= 1 && ty >= 1;
-    const int64_t col = (int64_t)j * g.P + i;           // only used when valid
+    // Every load is issued unconditionally from an address clamped into the
+    // padded box (always inside the allocation); values of positions outside
+    // a field's extent are replaced by zero where they are consumed.  This
+    // keeps the loads branch-free so that a whole plane's worth is in flight
+    // at once.
+    const int ic = min(max(i, 0), g.nx), jc = min(max(j, 0), g.ny);
+    const int64_t col = (int64_t)jc * g.P + ic;
+    auto at = [&](int k) -> int64_t { return (int64_t)min(max(k, 0), g.nz) * g.S + col; };
 
-    auto ld = [&](const double* a, bool ok, int k) -> double {
-        return ok ? a[(int64_t)k * g.S + col] : 0.0;
+    // queue set of a plane (own column): needed at planes p-1..p+1
+    struct QSet { double vx, vy, vz, pf, kc, lp, mu; };
+    // cell set of a plane: needed at plane p only
+    struct CSet { double pt, pto, pfo, eta, lpo, rx, ry, rz, fox, foy, foz; };
+    auto load_q = [&](int k, QSet& q) {
+        const int64_t o = at(k);
+        q.vx = p.vx[o]; q.vy = p.vy[o]; q.vz = p.vz[o]; q.pf = p.pf[o];
+        q.kc = p.kc[o]; q.lp = p.lp[o]; q.mu = p.mus[o];
+    };
+    auto load_c = [&](int k, CSet& c) {
+        const int64_t o = at(k);
+        c.pt = p.pt[o]; c.pto = p.pto[o]; c.pfo = p.pfo[o]; c.eta = p.eta[o];
+        c.lpo = UPD_LP ? p.lpo[o] : 0.0;
+        c.rx = p.rx[o]; c.ry = p.ry[o]; c.rz = p.rz[o];
+        c.fox = p.fox[o]; c.foy = p.foy[o]; c.foz = p.foz[o];
+    };
+    auto mask_q = [&](int k, QSet& q) {
+        const bool pk = (k >= 0) && (k < g.nz);
+        q.vx = (vxcol && pk) ? q.vx : 0.0;
+        q.vy = (vycol && pk) ? q.vy : 0.0;
+        q.vz = (cell && k >= 0 && k <= g.nz) ? q.vz : 0.0;
+        q.pf = (cell && pk) ? q.pf : 0.0;
+        q.kc = (cell && pk) ? q.kc : 0.0;
+        q.lp = (cell && pk) ? q.lp : 0.0;
+        q.mu = (cell && pk) ? q.mu : 0.0;
     };
 
     // register queue (own column): _p = plane p-1, _c = plane p, _n = plane p+1
@@ -85,17 +115,17 @@ __global__ __launch_bounds__(BX * BY) void k_iter(Geom g, Coef c, IterPtrs p) {
 #pragma unroll
     for (int q = 0; q < NNORM; ++q) nm[q] = 0.0;
 
+    QSet qn;     // plane p+1 (prefetched one step ahead)
+    CSet cc;     // cell set of plane p (prefetched one step ahead)
     {
         const int p0 = kz0 - 1;
-        const bool pl = p0 >= 0;
-        vx_c = ld(p.vx, vxcol && pl, p0);
-        vy_c = ld(p.vy, vycol && pl, p0);
-        vz_c = ld(p.vz, cell && pl, p0);
-        pf_c = ld(p.pf, cell && pl, p0);
-        kc_c = ld(p.kc, cell && pl, p0);
-        lp_c = ld(p.lp, cell && pl, p0);
-        s_c = (cell && pl) ? exp(lp_c) : 0.0;
-        mu_c = ld(p.mus, cell && pl, p0);
+        QSet q0;
+        load_q(p0, q0);
+        load_q(p0 + 1, qn);
+        load_c(p0, cc);
+        mask_q(p0, q0);
+        vx_c = q0.vx; vy_c = q0.vy; vz_c = q0.vz; pf_c = q0.pf; kc_c = q0.kc; lp_c = q0.lp; mu_c = q0.mu;
+        s_c = (cell && p0 >= 0) ? exp(lp_c) : 0.0;
     }
 
     for (int pz = kz0 - 1; pz < kz1; ++pz) {
@@ -103,30 +133,23 @@ __global__ __launch_bounds__(BX * BY) void k_iter(Geom g, Coef c, IterPtrs p) {
         const bool pln = pz + 1 < g.nz;          // plane pz+1 is a real plane
         const bool live = pz >= kz0;             // outputs of this plane belong to the block
 
-        // plane pz+1 for the queue
-        const double vx_n = ld(p.vx, vxcol && pln, pz + 1);
-        const double vy_n = ld(p.vy, vycol && pln, pz + 1);
-        const double vz_n = ld(p.vz, cell && (pz + 1 <= g.nz), pz + 1);
-        const double pf_n = ld(p.pf, cell && pln, pz + 1);
-        const double kc_n = ld(p.kc, cell && pln, pz + 1);
-        const double lp_n = ld(p.lp, cell && pln, pz + 1);
-        const double mu_n = ld(p.mus, cell && pln, pz + 1);
+        // prefetch what the next step needs
+        QSet qnn;
+        CSet cn;
+        load_q(pz + 2, qnn);
+        load_c(pz + 1, cn);
+
+        // plane pz+1 for the queue (arrived during the previous step)
+        mask_q(pz + 1, qn);
+        const double vx_n = qn.vx, vy_n = qn.vy, vz_n = qn.vz, pf_n = qn.pf, kc_n = qn.kc;
+        const double lp_n = qn.lp, mu_n = qn.mu;
         const double s_n = (cell && pln) ? exp(lp_n) : 0.0;
 
         // plane pz values needed for the cell quantities
         const bool cq = cellq && plc;
         const bool oc = outc && plc && live;
-        const double pt = ld(p.pt, cq, pz);
-        const double pto = ld(p.pto, cq, pz);
-        const double pfo = ld(p.pfo, cq, pz);
-        const double eta = ld(p.eta, cq, pz);
-        const double lpo = UPD_LP ? ld(p.lpo, oc, pz) : 0.0;
-        const double rx = ld(p.rx, oc, pz);
-        const double ry = ld(p.ry, oc, pz);
-        const double rz = ld(p.rz, oc, pz);
-        const double fox = ld(p.fox, oc, pz);
-        const double foy = ld(p.foy, oc, pz);
-        const double foz = ld(p.foz, oc, pz);
+        const double pt = cc.pt, pto = cc.pto, pfo = cc.pfo, eta = cc.eta, lpo = cc.lpo;
+        const double rx = cc.rx, ry = cc.ry, rz = cc.rz, fox = cc.fox, foy = cc.foy, foz = cc.foz;
 
         sh.vx[ty][tx] = vx_c;
         sh.vy[ty][tx] = vy_c;
@@ -305,6 +328,8 @@ __global__ __launch_bounds__(BX * BY) void k_iter(Geom g, Coef c, IterPtrs p) {
         lp_c = lp_n;
         ptn_p = ptn; tzz_p = tzz; rg_p = rg; w_p = w;
         txz_c = txz_n; tyz_c = tyz_n;
+        qn = qnn;
+        cc = cn;
     }
 
     if (NORMS) {
