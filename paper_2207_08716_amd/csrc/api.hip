@@ -105,6 +105,9 @@ RefreshCoef make_refresh(const pt_grid* g, double r_eta, double r_mu) {
     return r;
 }
 
+int64_t ws_scratch_offset(const pt_grid* g);
+size_t ws_needed(const pt_grid* g);
+
 double* cur(pt_grid* g, int f) { return f < PT_NPING ? g->f[f][g->cur[f]] : g->f[f][0]; }
 double* alt(pt_grid* g, int f) { return g->f[f][1 - g->cur[f]]; }
 
@@ -142,6 +145,13 @@ AuxPtrs aux(pt_grid* g) {
     a.mus = cur(g, PT_MUS);
     a.k0 = g->f[PT_K0][0];
     a.lp_o = alt(g, PT_LP);
+    if (g->ws) {
+        const int64_t box = g->geom.S * (int64_t)(g->geom.nz + 1);
+        double* base = static_cast<double*>(g->ws) + ws_scratch_offset(g);
+        a.scr0 = base;
+        a.scr1 = base + box;
+        a.scr2 = base + 2 * box;
+    }
     return a;
 }
 
@@ -153,11 +163,20 @@ const std::initializer_list<int> kAllCore = {PT_VX, PT_VY, PT_VZ, PT_PT, PT_PF, 
 pt_status check_ready(pt_grid* g) {
     if (!bound(g, kAllCore, true)) return fail(g, PT_EINVAL, "not every field (both copies of the iterated ones) is bound");
     if ((g->prm.flags & PT_F_K0FIELD) && !g->f[PT_K0][0]) return fail(g, PT_EINVAL, "PT_F_K0FIELD set but PT_K0 not bound");
+    if (!g->ws || g->ws_bytes < ws_needed(g)) return fail(g, PT_EINVAL, "workspace not bound or too small");
     return PT_OK;
 }
 
+// Workspace layout (doubles): [partials: n_blocks * 8][norms: 8][pad to 256 B]
+// [three padded-box scratch fields for the refresh passes].
+int64_t ws_scratch_offset(const pt_grid* g) {
+    const int64_t head = iter_grid_blocks(g->geom) * NNORM + NNORM;
+    return (head + 31) / 32 * 32;
+}
+
 size_t ws_needed(const pt_grid* g) {
-    return (size_t)(iter_grid_blocks(g->geom) * NNORM + NNORM) * sizeof(double);
+    const int64_t box = g->geom.S * (int64_t)(g->geom.nz + 1);
+    return (size_t)(ws_scratch_offset(g) + 3 * box) * sizeof(double);
 }
 
 pt_status refresh_impl(pt_grid* g, double r_eta, double r_mu) {

@@ -90,12 +90,18 @@ __global__ __launch_bounds__(BX * BY) void k_iter(Geom g, Coef c, IterPtrs p) {
         q.vx = p.vx[o]; q.vy = p.vy[o]; q.vz = p.vz[o]; q.pf = p.pf[o];
         q.kc = p.kc[o]; q.lp = p.lp[o]; q.mu = p.mus[o];
     };
+    // The cell set is loaded only by the threads that use it (halo columns
+    // would otherwise fetch tile-only fields from HBM a second time).
     auto load_c = [&](int k, CSet& c) {
         const int64_t o = at(k);
-        c.pt = p.pt[o]; c.pto = p.pto[o]; c.pfo = p.pfo[o]; c.eta = p.eta[o];
-        c.lpo = UPD_LP ? p.lpo[o] : 0.0;
-        c.rx = p.rx[o]; c.ry = p.ry[o]; c.rz = p.rz[o];
-        c.fox = p.fox[o]; c.foy = p.foy[o]; c.foz = p.foz[o];
+        if (cellq) {
+            c.pt = p.pt[o]; c.pto = p.pto[o]; c.pfo = p.pfo[o]; c.eta = p.eta[o];
+        }
+        if (outc) {
+            c.lpo = UPD_LP ? p.lpo[o] : 0.0;
+            c.rx = p.rx[o]; c.ry = p.ry[o]; c.rz = p.rz[o];
+            c.fox = p.fox[o]; c.foy = p.foy[o]; c.foz = p.foz[o];
+        }
     };
     auto mask_q = [&](int k, QSet& q) {
         const bool pk = (k >= 0) && (k < g.nz);
@@ -116,7 +122,7 @@ __global__ __launch_bounds__(BX * BY) void k_iter(Geom g, Coef c, IterPtrs p) {
     for (int q = 0; q < NNORM; ++q) nm[q] = 0.0;
 
     QSet qn;     // plane p+1 (prefetched one step ahead)
-    CSet cc;     // cell set of plane p (prefetched one step ahead)
+    CSet cc{};   // cell set of plane p (prefetched one step ahead)
     {
         const int p0 = kz0 - 1;
         QSet q0;
@@ -135,7 +141,7 @@ __global__ __launch_bounds__(BX * BY) void k_iter(Geom g, Coef c, IterPtrs p) {
 
         // prefetch what the next step needs
         QSet qnn;
-        CSet cn;
+        CSet cn = cc;
         load_q(pz + 2, qnn);
         load_c(pz + 1, cn);
 

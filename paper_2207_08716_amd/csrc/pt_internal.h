@@ -72,6 +72,7 @@ struct AuxPtrs {
     double *mn, *kc, *eta, *mus;
     const double* k0;
     double* lp_o;                  // porosity step output
+    double *scr0, *scr1, *scr2;    // three padded-box scratch fields (workspace)
 };
 
 struct RefreshCoef {
