@@ -12,7 +12,8 @@ value = T_eff = A_eff / t_it with A_eff = (2*12 + 1) N p (eqs (37)-(38)),
 N = 511^3 cells, p = 8 bytes.
 
 Prints one JSON line.  Options: --gpus N (only 1: the build runs on one GPU),
---steps K, --warmup W, --n (grid size), --no-cpu (skip the CPU baseline).
+--steps K, --warmup W, --n (grid size), --no-cpu (skip the CPU baseline),
+--ttt-n (size of the mixed-vs-FP64 time-to-tolerance comparison; 0 skips it).
 """
 from __future__ import annotations
 
@@ -75,6 +76,68 @@ def cpu_baseline(cfg, fields, n_iter: int = 2):
     }
 
 
+def time_to_tol(n: int, rtol: float = 1e-8, n_picard: int = 5, eta_in: float = 1e-4):
+    """Wall time of one physical step of the Picard schedule (n_picard stages,
+    each linear solve to a relative residual rtol) on the mixed workload at n^3:
+    FP64 PT sweeps against FP32 sweeps inside FP64 defect correction, on the
+    same GPU, from the same initial state."""
+    import numpy as np
+    import torch
+    from paper_2207_08716_amd import inputs, schedules
+
+    cfg = inputs.config_mixed(n)
+    f = inputs.initial_fields(cfg)
+    # load every kernel once on a small grid so that timing excludes code loading
+    warm_cfg = inputs.config_mixed(16)
+    wf = inputs.initial_fields(warm_cfg)
+    w = schedules.make_grid(warm_cfg, wf)
+    w.begin_step(False)
+    w.refresh(1.0, 1.0)
+    w.solve_linear(1e-2, 1000)
+    w.solve_mixed(1e-2, 1e-1, 1000, 2)
+    w.porosity_step()
+    torch.cuda.synchronize()
+    del w
+
+    out = {"n": n, "rtol": rtol, "picard_stages": n_picard, "eta_in": eta_in,
+           "dt": cfg.phys.dt, "workload": f"{n}^3 two-anomaly grid, lognormal k0, DP cap; one Picard step"}
+    fields = {}
+    for mode in ("fp64", "mixed"):
+        g = schedules.make_grid(cfg, f)
+        if mode == "mixed":
+            g.enable_mixed()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.begin_step(False)
+        its = []
+        ok_all = True
+        for _ in range(n_picard):
+            g.refresh(1.0, 1.0)
+            if mode == "fp64":
+                it, rho, ok = g.solve_linear(rtol, 2_000_000)
+                its.append(it)
+            else:
+                inner, outer, rho, ok = g.solve_mixed(rtol, eta_in, 2_000_000, 60)
+                its.append([inner, outer])
+            ok_all = ok_all and ok
+            g.porosity_step()
+        torch.cuda.synchronize()
+        out[f"{mode}_s"] = round(time.perf_counter() - t0, 3)
+        out[f"{mode}_iters"] = its
+        out[f"{mode}_converged"] = ok_all
+        fields[mode] = {k: g.get(k) for k in ("vx", "vy", "vz", "pt", "pf", "lp")}
+        g.close()
+        del g
+        torch.cuda.empty_cache()
+    out["speedup_mixed_vs_fp64"] = round(out["fp64_s"] / out["mixed_s"], 3)
+    rel = {}
+    for k in fields["fp64"]:
+        a, b = fields["mixed"][k], fields["fp64"][k]
+        rel[k] = float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+    out["mixed_vs_fp64_rel_field_diff"] = rel
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +146,8 @@ def main(argv=None):
     ap.add_argument("--n", type=int, default=511)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=2)
+    ap.add_argument("--ttt-n", type=int, default=127,
+                    help="grid size of the mixed-vs-FP64 time-to-tolerance comparison (0: skip)")
     args = ap.parse_args(argv)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -187,6 +252,8 @@ def main(argv=None):
     g.close()
     del g
     torch.cuda.empty_cache()
+
+    out["time_to_tol"] = time_to_tol(args.ttt_n) if args.ttt_n > 0 else None
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, fields, args.cpu_iters)

@@ -195,6 +195,28 @@ pt_status pt_solve_linear(pt_grid* g, double rtol, int64_t max_iter,
  * fraction. */
 pt_status pt_porosity_step(pt_grid* g);
 
+/* ---- Mixed precision (FP32 sweeps inside FP64 defect correction) --------
+ * FP32 workspace for the correction system: query the size (24 FP32 padded
+ * boxes), then bind a device buffer (256-byte aligned) of at least that many
+ * bytes.  The library clears it before first use. */
+pt_status pt_mixed_workspace_size(const pt_grid* g, size_t* bytes);
+pt_status pt_bind_mixed_workspace(pt_grid* g, void* dev_ptr, size_t bytes);
+
+/* FP64 residuals f, r_Pt, r_Pf of the present state with the present
+ * coefficients (the quantities whose infinity norms pt_solve_linear tests),
+ * written to the mixed workspace in FP32; norms via pt_last_norms.  Needs the
+ * mixed workspace. */
+pt_status pt_residual(pt_grid* g);
+
+/* One linear Picard stage solved by defect correction (coefficients and
+ * porosity frozen, as pt_solve_linear): repeat { r = residual of x in FP64;
+ * stop when rho = max(g_V/g_V0, g_P/g_P0) <= rtol; solve A d = -r by FP32 PT
+ * sweeps from d = 0 until the correction residual falls to eta_in times r
+ * (checked every nup sweeps) or max_inner sweeps; x += d in FP64 }.  At most
+ * max_outer corrections.  Synchronises.  PT_ENOTCONV if rtol is not met. */
+pt_status pt_solve_mixed(pt_grid* g, double rtol, double eta_in, int64_t max_inner, int32_t max_outer,
+                         int64_t* inner_iters, int32_t* outer_iters, double* rho);
+
 /* Streaming copy of n doubles (achievable-bandwidth reference). */
 pt_status pt_copy(pt_grid* g, const void* src, void* dst, int64_t n);
 

@@ -17,6 +17,9 @@ struct pt_grid {
     int cur[PT_NPING];
     void* ws = nullptr;
     size_t ws_bytes = 0;
+    float* mws = nullptr;      // FP32 workspace of the mixed-precision solve
+    size_t mws_bytes = 0;
+    bool mws_clean = false;    // both correction copies zeroed once
     hipStream_t stream = nullptr;
     int64_t iter = 0;          // iteration count within the current step
     bool refreshed = false;    // any refresh done on this handle
@@ -190,8 +193,8 @@ pt_status refresh_impl(pt_grid* g, double r_eta, double r_mu) {
     return PT_OK;
 }
 
-pt_status iteration_impl(pt_grid* g, int update_lp, int norms) {
-    IterPtrs p{};
+SweepPtrs<double> sweep_ptrs(pt_grid* g) {
+    SweepPtrs<double> p{};
     p.vx = cur(g, PT_VX); p.vy = cur(g, PT_VY); p.vz = cur(g, PT_VZ);
     p.pt = cur(g, PT_PT); p.pf = cur(g, PT_PF); p.lp = cur(g, PT_LP);
     p.rx = cur(g, PT_RX); p.ry = cur(g, PT_RY); p.rz = cur(g, PT_RZ);
@@ -202,14 +205,25 @@ pt_status iteration_impl(pt_grid* g, int update_lp, int norms) {
     p.pt_o = alt(g, PT_PT); p.pf_o = alt(g, PT_PF); p.lp_o = alt(g, PT_LP);
     p.rx_o = alt(g, PT_RX); p.ry_o = alt(g, PT_RY); p.rz_o = alt(g, PT_RZ);
     p.partials = static_cast<double*>(g->ws);
-    hipError_t e = launch_iteration(g->geom, g->coef, p, update_lp, norms, g->stream);
+    return p;
+}
+
+pt_status reduce_norms(pt_grid* g) {
+    const int64_t nb = iter_grid_blocks(g->geom);
+    double* out = static_cast<double*>(g->ws) + nb * NNORM;
+    hipError_t e = launch_reduce_max(static_cast<double*>(g->ws), nb, out, g->stream);
+    if (e != hipSuccess) return hip_fail(g, e, "reduce");
+    g->norms_pending = true;
+    return PT_OK;
+}
+
+pt_status iteration_impl(pt_grid* g, int update_lp, int norms) {
+    const SweepPtrs<double> p = sweep_ptrs(g);
+    hipError_t e = launch_iteration(g->geom, g->coef, p, update_lp ? MD_THESIS : MD_LINEAR, norms, g->stream);
     if (e != hipSuccess) return hip_fail(g, e, "iteration");
     if (norms) {
-        const int64_t nb = iter_grid_blocks(g->geom);
-        double* out = static_cast<double*>(g->ws) + nb * NNORM;
-        e = launch_reduce_max(static_cast<double*>(g->ws), nb, out, g->stream);
-        if (e != hipSuccess) return hip_fail(g, e, "reduce");
-        g->norms_pending = true;
+        pt_status st = reduce_norms(g);
+        if (st != PT_OK) return st;
     }
     for (int f = 0; f < PT_NPING; ++f) {
         if (f == PT_LP && !update_lp) continue;
@@ -218,6 +232,17 @@ pt_status iteration_impl(pt_grid* g, int update_lp, int norms) {
     g->iter += 1;
     return PT_OK;
 }
+
+// ---- mixed precision workspace --------------------------------------------
+// FP32 padded boxes: [0..7] correction copy 0 (dvx dvy dvz dpt dpf drx dry drz),
+// [8..15] copy 1, [16..20] residual of x (fx fy fz rpt rpf), [21] k, [22] mu_s,
+// [23] chi.
+constexpr int MX_NBOX = 24;
+constexpr int MX_RES = 16;
+
+int64_t mx_box(const pt_grid* g) { return g->geom.S * (int64_t)(g->geom.nz + 1); }
+size_t mx_needed(const pt_grid* g) { return (size_t)(MX_NBOX * mx_box(g)) * sizeof(float); }
+float* mx(pt_grid* g, int b) { return g->mws + (int64_t)b * mx_box(g); }
 
 pt_status read_norms(pt_grid* g, pt_norms* out) {
     const int64_t nb = iter_grid_blocks(g->geom);
@@ -268,6 +293,8 @@ pt_status pt_create(int32_t nx, int32_t ny, int32_t nz, int64_t row_pitch, const
     g->geom.nz = nz;
     g->geom.P = row_pitch;
     g->geom.S = row_pitch * (int64_t)(ny + 1);
+    g->geom.kz = KZ_MAX;
+    g->geom.kz = choose_kz(g->geom);
     g->prm = *params;
     std::memset(g->f, 0, sizeof(g->f));
     std::memset(g->cur, 0, sizeof(g->cur));
@@ -426,6 +453,141 @@ pt_status pt_porosity_step(pt_grid* g) {
     if (e != hipSuccess) return hip_fail(g, e, "porosity_step");
     g->cur[PT_LP] ^= 1;
     return PT_OK;
+}
+
+pt_status pt_mixed_workspace_size(const pt_grid* g, size_t* bytes) {
+    if (!g || !bytes) return PT_EINVAL;
+    *bytes = mx_needed(g);
+    return PT_OK;
+}
+
+pt_status pt_bind_mixed_workspace(pt_grid* g, void* dev_ptr, size_t bytes) {
+    if (!g) return PT_EINVAL;
+    if (!dev_ptr || (reinterpret_cast<uintptr_t>(dev_ptr) & 255u) || bytes < mx_needed(g))
+        return fail(g, PT_EINVAL, "mixed workspace missing, unaligned or too small");
+    g->mws = static_cast<float*>(dev_ptr);
+    g->mws_bytes = bytes;
+    g->mws_clean = false;
+    return PT_OK;
+}
+
+pt_status pt_residual(pt_grid* g) {
+    if (!g) return PT_EINVAL;
+    pt_status st = check_ready(g);
+    if (st != PT_OK) return st;
+    if (!g->mws) return fail(g, PT_EINVAL, "mixed workspace not bound");
+    SweepPtrs<double> p = sweep_ptrs(g);
+    p.res_fx = mx(g, MX_RES + 0);
+    p.res_fy = mx(g, MX_RES + 1);
+    p.res_fz = mx(g, MX_RES + 2);
+    p.res_rpt = mx(g, MX_RES + 3);
+    p.res_rpf = mx(g, MX_RES + 4);
+    hipError_t e = launch_iteration(g->geom, g->coef, p, MD_RESID, 1, g->stream);
+    if (e != hipSuccess) return hip_fail(g, e, "residual");
+    return reduce_norms(g);
+}
+
+namespace {
+
+pt_status correction_sweep(pt_grid* g, int cp, int norms) {
+    SweepPtrs<float> p{};
+    const int src = cp ? 8 : 0, dst = cp ? 0 : 8;
+    p.vx = mx(g, src + 0); p.vy = mx(g, src + 1); p.vz = mx(g, src + 2);
+    p.pt = mx(g, src + 3); p.pf = mx(g, src + 4);
+    p.rx = mx(g, src + 5); p.ry = mx(g, src + 6); p.rz = mx(g, src + 7);
+    p.vx_o = mx(g, dst + 0); p.vy_o = mx(g, dst + 1); p.vz_o = mx(g, dst + 2);
+    p.pt_o = mx(g, dst + 3); p.pf_o = mx(g, dst + 4);
+    p.rx_o = mx(g, dst + 5); p.ry_o = mx(g, dst + 6); p.rz_o = mx(g, dst + 7);
+    p.fox = mx(g, MX_RES + 0); p.foy = mx(g, MX_RES + 1); p.foz = mx(g, MX_RES + 2);
+    p.pto = mx(g, MX_RES + 3); p.pfo = mx(g, MX_RES + 4);
+    p.kc = mx(g, 21); p.mus = mx(g, 22); p.eta = mx(g, 23);
+    p.partials = static_cast<double*>(g->ws);
+    hipError_t e = launch_correction(g->geom, g->coef, p, norms, g->stream);
+    if (e != hipSuccess) return hip_fail(g, e, "correction sweep");
+    if (norms) return reduce_norms(g);
+    return PT_OK;
+}
+
+MixedPtrs mixed_ptrs(pt_grid* g, int cp) {
+    MixedPtrs m{};
+    m.vx = cur(g, PT_VX); m.vy = cur(g, PT_VY); m.vz = cur(g, PT_VZ);
+    m.pt = cur(g, PT_PT); m.pf = cur(g, PT_PF);
+    m.lp = cur(g, PT_LP); m.kc = cur(g, PT_KC); m.eta = cur(g, PT_ETA); m.mus = cur(g, PT_MUS);
+    const int b = cp ? 8 : 0;
+    m.dvx = mx(g, b + 0); m.dvy = mx(g, b + 1); m.dvz = mx(g, b + 2);
+    m.dpt = mx(g, b + 3); m.dpf = mx(g, b + 4);
+    m.kc32 = mx(g, 21); m.mus32 = mx(g, 22); m.chi32 = mx(g, 23);
+    return m;
+}
+
+double group_rho(const pt_norms& nm, double g0v, double g0p) {
+    double r = 0.0;
+    if (g0v > 0.0) r = std::fmax(r, nm.f / g0v);
+    if (g0p > 0.0) r = std::fmax(r, std::fmax(nm.rpt, nm.rpf) / g0p);
+    return r;
+}
+
+}  // namespace
+
+pt_status pt_solve_mixed(pt_grid* g, double rtol, double eta_in, int64_t max_inner, int32_t max_outer,
+                         int64_t* inner_iters, int32_t* outer_iters, double* rho) {
+    if (!g || !(rtol > 0.0) || !(eta_in > 0.0 && eta_in < 1.0) || max_inner < 1 || max_outer < 1)
+        return PT_EINVAL;
+    pt_status st = check_ready(g);
+    if (st != PT_OK) return st;
+    if (!g->mws) return fail(g, PT_EINVAL, "mixed workspace not bound");
+    if (g->prm.flags & PT_F_MECHOFF) return fail(g, PT_EINVAL, "mixed precision does not support PT_F_MECHOFF");
+    const int64_t box_bytes = mx_box(g) * (int64_t)sizeof(float);
+    hipError_t e;
+    if (!g->mws_clean) {
+        e = hipMemsetAsync(g->mws, 0, 16 * box_bytes, g->stream);
+        if (e != hipSuccess) return hip_fail(g, e, "mixed workspace clear");
+        g->mws_clean = true;
+    }
+    e = launch_prepare_mixed(g->geom, mixed_ptrs(g, 0), g->stream);
+    if (e != hipSuccess) return hip_fail(g, e, "prepare mixed");
+    const int64_t nup = g->prm.nup;
+    double g0v = 0.0, g0p = 0.0, r = INFINITY;
+    int64_t inner_total = 0;
+    int32_t outer = 0;
+    for (;;) {
+        st = pt_residual(g);
+        if (st != PT_OK) return st;
+        pt_norms nm;
+        st = read_norms(g, &nm);
+        if (st != PT_OK) return st;
+        if (outer == 0) {
+            g0v = nm.f;
+            g0p = std::fmax(nm.rpt, nm.rpf);
+        }
+        r = group_rho(nm, g0v, g0p);
+        if (r <= rtol || outer >= max_outer) break;
+        const double gv = nm.f, gp = std::fmax(nm.rpt, nm.rpf);
+        // correction d = 0, damped residual 0 (copy 0 holds the present d)
+        e = hipMemsetAsync(mx(g, 0), 0, 8 * box_bytes, g->stream);
+        if (e != hipSuccess) return hip_fail(g, e, "correction clear");
+        int cp = 0;
+        for (int64_t m = 1; m <= max_inner; ++m) {
+            const bool chk = (m % nup == 0);
+            st = correction_sweep(g, cp, chk ? 1 : 0);
+            if (st != PT_OK) return st;
+            cp ^= 1;
+            ++inner_total;
+            if (chk) {
+                pt_norms ni;
+                st = read_norms(g, &ni);
+                if (st != PT_OK) return st;
+                if (group_rho(ni, gv, gp) <= eta_in) break;
+            }
+        }
+        e = launch_apply_correction(g->geom, mixed_ptrs(g, cp), g->stream);
+        if (e != hipSuccess) return hip_fail(g, e, "apply correction");
+        ++outer;
+    }
+    if (inner_iters) *inner_iters = inner_total;
+    if (outer_iters) *outer_iters = outer;
+    if (rho) *rho = r;
+    return (r <= rtol) ? PT_OK : PT_ENOTCONV;
 }
 
 pt_status pt_copy(pt_grid* g, const void* src, void* dst, int64_t n) {

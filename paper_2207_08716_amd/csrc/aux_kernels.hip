@@ -299,6 +299,34 @@ __global__ void k_copy_tail(const double* __restrict__ src, double* __restrict__
     if (threadIdx.x == 0 && n % 2 == 1) dst[n - 1] = src[n - 1];
 }
 
+// Mixed precision, once per Picard stage: FP32 copies of k/mu_f and mu_s,
+// and chi = 1/((1-phi) eta_phi) with the porosity frozen for the stage.
+__global__ __launch_bounds__(AB) void k_prepare_mixed(Geom g, MixedPtrs m) {
+    Idx q;
+    if (!box_index(g, (int64_t)blockIdx.x * AB + threadIdx.x, q)) return;
+    if (q.i >= g.nx || q.j >= g.ny || q.k >= g.nz) return;
+    const int64_t o = at(g, q.i, q.j, q.k);
+    m.kc32[o] = float(m.kc[o]);
+    m.mus32[o] = float(m.mus[o]);
+    m.chi32[o] = float(1.0 / (m.eta[o] * exp(m.lp[o])));
+}
+
+// Defect correction x <- x + d in FP64 (velocity faces, pressures).  The
+// correction is zero on boundary faces and outside every extent.
+__global__ __launch_bounds__(AB) void k_apply_correction(Geom g, MixedPtrs m) {
+    Idx q;
+    if (!box_index(g, (int64_t)blockIdx.x * AB + threadIdx.x, q)) return;
+    const int i = q.i, j = q.j, k = q.k;
+    const int64_t o = at(g, i, j, k);
+    if (j < g.ny && k < g.nz && i >= 1 && i < g.nx) m.vx[o] += double(m.dvx[o]);
+    if (i < g.nx && k < g.nz && j >= 1 && j < g.ny) m.vy[o] += double(m.dvy[o]);
+    if (i < g.nx && j < g.ny && k >= 1 && k < g.nz) m.vz[o] += double(m.dvz[o]);
+    if (i < g.nx && j < g.ny && k < g.nz) {
+        m.pt[o] += double(m.dpt[o]);
+        m.pf[o] += double(m.dpf[o]);
+    }
+}
+
 inline dim3 box_grid(const Geom& g) {
     const int64_t n = (int64_t)(g.nx + 1) * (g.ny + 1) * (g.nz + 1);
     return dim3((unsigned)((n + AB - 1) / AB));
@@ -327,6 +355,16 @@ hipError_t launch_fo(const Geom& g, const Coef& c, const RefreshCoef& r, const A
 
 hipError_t launch_porosity_step(const Geom& g, const Coef& c, const AuxPtrs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_porosity, box_grid(g), dim3(AB), 0, s, g, c, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_prepare_mixed(const Geom& g, const MixedPtrs& m, hipStream_t s) {
+    hipLaunchKernelGGL(k_prepare_mixed, box_grid(g), dim3(AB), 0, s, g, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_apply_correction(const Geom& g, const MixedPtrs& m, hipStream_t s) {
+    hipLaunchKernelGGL(k_apply_correction, box_grid(g), dim3(AB), 0, s, g, m);
     return hipGetLastError();
 }
 

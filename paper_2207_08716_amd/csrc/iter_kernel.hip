@@ -1,4 +1,4 @@
-// Fused pseudo-transient iteration for gfx950.
+// Fused pseudo-transient sweep for gfx950.
 //
 // One launch performs a whole PT iteration (thesis article 1, section 2.2):
 // total-pressure update (eq (17)), Darcy flux and fluid-pressure update
@@ -6,8 +6,17 @@
 // (eq (19)) and the porosity update in log space (eq (22)), all from the
 // iteration-k state (Jacobi), with the boundary conditions of eqs (33)-(34).
 //
+// Modes of the same sweep:
+//   THESIS  FP64, porosity updated every iteration (thesis schedule);
+//   LINEAR  FP64, porosity frozen (one linear system of a Picard stage);
+//   RESID   FP64, no update: writes the residuals f, r_Pt, r_Pf of the present
+//           state (physical stress, current Pt) in FP32 for defect correction;
+//   CORR    FP32 sweep on the correction system A(c) d = -r of a Picard stage:
+//           the same iteration applied to x + d, with the FP64 residual of x as
+//           right-hand side (no old values, no buoyancy, no history term).
+//
 // Work decomposition.  A BX x BY block owns a column of (BX-2) x (BY-2) cells
-// plus a one-cell halo ring and marches upward through a chunk of KZ planes.
+// plus a one-cell halo ring and marches upward through a chunk of g.kz planes.
 // Per plane the block
 //   1. stages the plane's velocities, fluid pressure, permeability, solid
 //      fraction and shear viscosity in LDS (values of plane p+1 that the
@@ -16,26 +25,42 @@
 //      low halo, shear stresses on edges, and Pf', ln(1-phi)' on the tile;
 //   3. after one more barrier, updates the three face velocities of every
 //      tile cell.
-// Stresses and Darcy fluxes never touch HBM.  Every field is read once and
-// the iterated fields written once per iteration (plus halo re-reads, which
-// mostly hit L2 because neighbouring tiles run together on one XCD).
+// The next plane's loads are issued one step ahead.  Stresses and Darcy
+// fluxes never touch HBM; the iterated fields are written once.
 #include "pt_internal.h"
 
 namespace ptk {
 
 namespace {
 
+template <typename T>
 struct Lds {
-    double vx[BY][BX], vy[BY][BX], vz1[BY][BX];
-    double pf[BY][BX], kc[BY][BX], s[BY][BX], mu[BY][BX], mu1[BY][BX];
-    double ptn[BY][BX], txx[BY][BX], tyy[BY][BX], txy[BY][BX], w[BY][BX];
-    double txz[2][BY][BX], tyz[2][BY][BX];
+    T vx[BY][BX], vy[BY][BX], vz1[BY][BX];
+    T pf[BY][BX], kc[BY][BX], s[BY][BX], mu[BY][BX], mu1[BY][BX];
+    T ptn[BY][BX], txx[BY][BX], tyy[BY][BX], txy[BY][BX], w[BY][BX];
+    T txz[2][BY][BX], tyz[2][BY][BX];
 };
 
-__device__ __forceinline__ double nanmax(double m, double v) {
+template <typename T>
+__device__ __forceinline__ T nanmax(T m, T v) {
     // maximum that lets a NaN through (divergence must not be hidden)
     return (v > m || v != v) ? v : m;
 }
+
+// Constants in the working precision of the sweep.
+template <typename T>
+struct CT {
+    T dxi, dyi, dzi, dt, dti, beta_d, alpha, beta_phi, rhofg, rhosg, rhobg, buoy, gdts_inv, beta_n,
+        rho_i_inv, dtauv_c, dtaupt_c, dtaupf_c, dampx, dampy, dampz, ab, third;
+    int mech_off;
+    __device__ explicit CT(const Coef& c)
+        : dxi(T(c.dxi)), dyi(T(c.dyi)), dzi(T(c.dzi)), dt(T(c.dt)), dti(T(c.dti)), beta_d(T(c.beta_d)),
+          alpha(T(c.alpha)), beta_phi(T(c.beta_phi)), rhofg(T(c.rhofg)), rhosg(T(c.rhosg)),
+          rhobg(T(c.rhobg)), buoy(T(c.buoy)), gdts_inv(T(c.gdts_inv)), beta_n(T(c.beta_n)),
+          rho_i_inv(T(c.rho_i_inv)), dtauv_c(T(c.dtauv_c)), dtaupt_c(T(c.dtaupt_c)),
+          dtaupf_c(T(c.dtaupf_c)), dampx(T(c.dampx)), dampy(T(c.dampy)), dampz(T(c.dampz)),
+          ab(T(c.ab)), third(T(c.third)), mech_off(c.mech_off) {}
+};
 
 // Tile order: consecutive tiles go to the same XCD (blocks are dealt to the
 // eight XCDs round robin), so tiles that share halo planes share an L2.
@@ -46,23 +71,29 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t L, int64_t total) {
     return (xcd < r) ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
 }
 
-template <bool UPD_LP, bool NORMS>
-__global__ __launch_bounds__(BX * BY) void k_iter(Geom g, Coef c, IterPtrs p) {
-    __shared__ Lds sh;
+template <typename T, int MODE, bool NORMS>
+__global__ __launch_bounds__(BX * BY) void k_sweep(Geom g, Coef cd, SweepPtrs<T> p) {
+    constexpr bool UPD_LP = (MODE == MD_THESIS);
+    constexpr bool RESID = (MODE == MD_RESID);
+    constexpr bool CORR = (MODE == MD_CORR);
+    constexpr bool WNORM = NORMS || RESID;
+    __shared__ Lds<T> sh;
+    const CT<T> c(cd);
+    const T zero = T(0), half = T(0.5), one = T(1), two = T(2), quarter = T(0.25);
 
     const int gx = (g.nx + BX - 3) / (BX - 2);
     const int gy = (g.ny + BY - 3) / (BY - 2);
     const int64_t total = (int64_t)gridDim.x;
-    const int64_t T = xcd_tile(blockIdx.x, total);
-    const int bx = (int)(T % gx);
-    const int by = (int)((T / gx) % gy);
-    const int bz = (int)(T / ((int64_t)gx * gy));
+    const int64_t Tt = xcd_tile(blockIdx.x, total);
+    const int bx = (int)(Tt % gx);
+    const int by = (int)((Tt / gx) % gy);
+    const int bz = (int)(Tt / ((int64_t)gx * gy));
 
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int i = bx * (BX - 2) - 1 + tx;
     const int j = by * (BY - 2) - 1 + ty;
-    const int kz0 = bz * KZ;
-    const int kz1 = min(g.nz, kz0 + KZ);
+    const int kz0 = bz * g.kz;
+    const int kz1 = min(g.nz, kz0 + g.kz);
 
     const bool ci = (i >= 0) && (i < g.nx);
     const bool cj = (j >= 0) && (j < g.ny);
@@ -72,54 +103,58 @@ __global__ __launch_bounds__(BX * BY) void k_iter(Geom g, Coef c, IterPtrs p) {
     const bool outc = cell && tx >= 1 && tx <= BX - 2 && ty >= 1 && ty <= BY - 2;
     const bool cellq = cell && tx <= BX - 2 && ty <= BY - 2;
     const bool edge = tx >= 1 && ty >= 1;
-    // Every load is issued unconditionally from an address clamped into the
-    // padded box (always inside the allocation); values of positions outside
-    // a field's extent are replaced by zero where they are consumed.  This
-    // keeps the loads branch-free so that a whole plane's worth is in flight
-    // at once.
+
+    // Every load is issued from an address clamped into the padded box
+    // (always inside the allocation); values of positions outside a field's
+    // extent are replaced by zero where they are consumed.  The loads are
+    // branch-free so that a whole plane's worth is in flight at once.
     const int ic = min(max(i, 0), g.nx), jc = min(max(j, 0), g.ny);
     const int64_t col = (int64_t)jc * g.P + ic;
     auto at = [&](int k) -> int64_t { return (int64_t)min(max(k, 0), g.nz) * g.S + col; };
 
     // queue set of a plane (own column): needed at planes p-1..p+1
-    struct QSet { double vx, vy, vz, pf, kc, lp, mu; };
+    struct QSet { T vx, vy, vz, pf, kc, lp, mu; };
     // cell set of a plane: needed at plane p only
-    struct CSet { double pt, pto, pfo, eta, lpo, rx, ry, rz, fox, foy, foz; };
+    struct CSet { T pt, pto, pfo, eta, lpo, rx, ry, rz, fox, foy, foz; };
     auto load_q = [&](int k, QSet& q) {
         const int64_t o = at(k);
         q.vx = p.vx[o]; q.vy = p.vy[o]; q.vz = p.vz[o]; q.pf = p.pf[o];
-        q.kc = p.kc[o]; q.lp = p.lp[o]; q.mu = p.mus[o];
+        q.kc = p.kc[o]; q.mu = p.mus[o];
+        q.lp = CORR ? zero : p.lp[o];
     };
     // The cell set is loaded only by the threads that use it (halo columns
     // would otherwise fetch tile-only fields from HBM a second time).
-    auto load_c = [&](int k, CSet& c) {
+    auto load_c = [&](int k, CSet& cs) {
         const int64_t o = at(k);
         if (cellq) {
-            c.pt = p.pt[o]; c.pto = p.pto[o]; c.pfo = p.pfo[o]; c.eta = p.eta[o];
+            cs.pt = p.pt[o]; cs.pto = p.pto[o]; cs.pfo = p.pfo[o]; cs.eta = p.eta[o];
         }
         if (outc) {
-            c.lpo = UPD_LP ? p.lpo[o] : 0.0;
-            c.rx = p.rx[o]; c.ry = p.ry[o]; c.rz = p.rz[o];
-            c.fox = p.fox[o]; c.foy = p.foy[o]; c.foz = p.foz[o];
+            cs.lpo = UPD_LP ? p.lpo[o] : zero;
+            if (!RESID) {
+                cs.rx = p.rx[o]; cs.ry = p.ry[o]; cs.rz = p.rz[o];
+            }
+            cs.fox = p.fox[o]; cs.foy = p.foy[o]; cs.foz = p.foz[o];
         }
     };
     auto mask_q = [&](int k, QSet& q) {
         const bool pk = (k >= 0) && (k < g.nz);
-        q.vx = (vxcol && pk) ? q.vx : 0.0;
-        q.vy = (vycol && pk) ? q.vy : 0.0;
-        q.vz = (cell && k >= 0 && k <= g.nz) ? q.vz : 0.0;
-        q.pf = (cell && pk) ? q.pf : 0.0;
-        q.kc = (cell && pk) ? q.kc : 0.0;
-        q.lp = (cell && pk) ? q.lp : 0.0;
-        q.mu = (cell && pk) ? q.mu : 0.0;
+        q.vx = (vxcol && pk) ? q.vx : zero;
+        q.vy = (vycol && pk) ? q.vy : zero;
+        q.vz = (cell && k >= 0 && k <= g.nz) ? q.vz : zero;
+        q.pf = (cell && pk) ? q.pf : zero;
+        q.kc = (cell && pk) ? q.kc : zero;
+        q.lp = (cell && pk) ? q.lp : zero;
+        q.mu = (cell && pk) ? q.mu : zero;
     };
+    auto solid = [&](bool ok, T lp) -> T { return CORR ? one : (ok ? T(exp(lp)) : zero); };
 
     // register queue (own column): _p = plane p-1, _c = plane p, _n = plane p+1
-    double vx_c, vy_c, vz_c, pf_p = 0.0, pf_c, kc_p = 0.0, kc_c, s_p = 0.0, s_c, mu_p = 0.0, mu_c, lp_c;
-    double ptn_p = 0.0, tzz_p = 0.0, rg_p = 0.0, w_p = 0.0, txz_c = 0.0, tyz_c = 0.0;
-    double nm[NNORM];
+    T vx_c, vy_c, vz_c, pf_p = zero, pf_c, kc_p = zero, kc_c, s_p = zero, s_c, mu_p = zero, mu_c, lp_c;
+    T ptn_p = zero, tzz_p = zero, rg_p = zero, w_p = zero, txz_c = zero, tyz_c = zero;
+    T nm[NNORM];
 #pragma unroll
-    for (int q = 0; q < NNORM; ++q) nm[q] = 0.0;
+    for (int q = 0; q < NNORM; ++q) nm[q] = zero;
 
     QSet qn;     // plane p+1 (prefetched one step ahead)
     CSet cc{};   // cell set of plane p (prefetched one step ahead)
@@ -131,7 +166,7 @@ __global__ __launch_bounds__(BX * BY) void k_iter(Geom g, Coef c, IterPtrs p) {
         load_c(p0, cc);
         mask_q(p0, q0);
         vx_c = q0.vx; vy_c = q0.vy; vz_c = q0.vz; pf_c = q0.pf; kc_c = q0.kc; lp_c = q0.lp; mu_c = q0.mu;
-        s_c = (cell && p0 >= 0) ? exp(lp_c) : 0.0;
+        s_c = solid(cell && p0 >= 0, lp_c);
     }
 
     for (int pz = kz0 - 1; pz < kz1; ++pz) {
@@ -147,15 +182,15 @@ __global__ __launch_bounds__(BX * BY) void k_iter(Geom g, Coef c, IterPtrs p) {
 
         // plane pz+1 for the queue (arrived during the previous step)
         mask_q(pz + 1, qn);
-        const double vx_n = qn.vx, vy_n = qn.vy, vz_n = qn.vz, pf_n = qn.pf, kc_n = qn.kc;
-        const double lp_n = qn.lp, mu_n = qn.mu;
-        const double s_n = (cell && pln) ? exp(lp_n) : 0.0;
+        const T vx_n = qn.vx, vy_n = qn.vy, vz_n = qn.vz, pf_n = qn.pf, kc_n = qn.kc;
+        const T lp_n = qn.lp, mu_n = qn.mu;
+        const T s_n = solid(cell && pln, lp_n);
 
         // plane pz values needed for the cell quantities
         const bool cq = cellq && plc;
         const bool oc = outc && plc && live;
-        const double pt = cc.pt, pto = cc.pto, pfo = cc.pfo, eta = cc.eta, lpo = cc.lpo;
-        const double rx = cc.rx, ry = cc.ry, rz = cc.rz, fox = cc.fox, foy = cc.foy, foz = cc.foz;
+        const T pt = cc.pt, pto = cc.pto, pfo = cc.pfo, eta = cc.eta, lpo = cc.lpo;
+        const T rx = cc.rx, ry = cc.ry, rz = cc.rz, fox = cc.fox, foy = cc.foy, foz = cc.foz;
 
         sh.vx[ty][tx] = vx_c;
         sh.vy[ty][tx] = vy_c;
@@ -168,95 +203,114 @@ __global__ __launch_bounds__(BX * BY) void k_iter(Geom g, Coef c, IterPtrs p) {
         __syncthreads();
 
         // ---- cell quantities: div V, Pt' (eq (17)), stresses (eq (21)) ----
-        double ptn = 0.0, txx = 0.0, tyy = 0.0, tzz = 0.0, rg = 0.0, w = 0.0, chi = 0.0;
-        double rpt_k = 0.0;
+        T ptn = zero, txx = zero, tyy = zero, tzz = zero, rg = zero, w = zero, chi = zero;
+        T rpt_k = zero;
         if (cq) {
-            const double dxv = (sh.vx[ty][tx + 1] - vx_c) * c.dxi;
-            const double dyv = (sh.vy[ty + 1][tx] - vy_c) * c.dyi;
-            const double dzv = (vz_n - vz_c) * c.dzi;
-            const double divv = dxv + dyv + dzv;
-            chi = 1.0 / (eta * s_c);
-            const double dtp = c.dtaupt_c * mu_c;
-            if (c.mech_off) {
-                ptn = pt;
+            const T dxv = (sh.vx[ty][tx + 1] - vx_c) * c.dxi;
+            const T dyv = (sh.vy[ty + 1][tx] - vy_c) * c.dyi;
+            const T dzv = (vz_n - vz_c) * c.dzi;
+            const T divv = dxv + dyv + dzv;
+            const T dtp = c.dtaupt_c * mu_c;
+            T rimp;
+            if constexpr (CORR) {
+                // d Pt' = [d Pt - dtau (div dV + r_Pt(x) - beta_d alpha dPf/dt - dPf chi)]
+                //         / (1 + dtau (beta_d/dt + chi)); chi is a stored field here
+                chi = eta;
+                ptn = (pt - dtp * (divv + pto - c.beta_d * c.alpha * pf_c * c.dti - pf_c * chi)) /
+                      (one + dtp * (c.beta_d * c.dti + chi));
+                rimp = pto + divv + c.beta_d * (ptn - c.alpha * pf_c) * c.dti + (ptn - pf_c) * chi;
+                if (WNORM) rpt_k = pto + divv + c.beta_d * (pt - c.alpha * pf_c) * c.dti + (pt - pf_c) * chi;
             } else {
-                ptn = (pt - dtp * (divv + c.beta_d * (-pto - c.alpha * (pf_c - pfo)) * c.dti - pf_c * chi)) /
-                      (1.0 + dtp * (c.beta_d * c.dti + chi));
+                chi = one / (eta * s_c);
+                if (RESID || c.mech_off) {
+                    ptn = pt;
+                } else {
+                    ptn = (pt - dtp * (divv + c.beta_d * (-pto - c.alpha * (pf_c - pfo)) * c.dti - pf_c * chi)) /
+                          (one + dtp * (c.beta_d * c.dti + chi));
+                }
+                rimp = divv + c.beta_d * ((ptn - pto) - c.alpha * (pf_c - pfo)) * c.dti + (ptn - pf_c) * chi;
+                if (WNORM) rpt_k = divv + c.beta_d * ((pt - pto) - c.alpha * (pf_c - pfo)) * c.dti + (pt - pf_c) * chi;
+                rg = c.rhofg * (one - s_c) + c.rhosg * s_c;
             }
-            const double rimp = divv + c.beta_d * ((ptn - pto) - c.alpha * (pf_c - pfo)) * c.dti + (ptn - pf_c) * chi;
-            const double xi = mu_c * c.gdts_inv;
-            const double b = 2.0 * mu_c / (1.0 + xi);
-            const double d3 = divv * c.third;
-            const double comp = c.beta_n * rimp;
+            const T xi = mu_c * c.gdts_inv;
+            const T b = two * mu_c / (one + xi);
+            const T d3 = divv * c.third;
+            const T comp = RESID ? zero : c.beta_n * rimp;
             txx = b * ((dxv - d3) + comp);
             tyy = b * ((dyv - d3) + comp);
             tzz = b * ((dzv - d3) + comp);
-            rg = c.rhofg * (1.0 - s_c) + c.rhosg * s_c;
-            if (NORMS) {
-                w = b * comp - ptn + pt;
-                rpt_k = divv + c.beta_d * ((pt - pto) - c.alpha * (pf_c - pfo)) * c.dti + (pt - pf_c) * chi;
-            }
+            if (NORMS) w = b * comp - ptn + pt;
         }
 
         // ---- Darcy flux and fluid pressure (eqs (18), (20)); porosity (eq (22)) ----
-        double pfn = 0.0, lpn = 0.0, rpf_k = 0.0;
+        T pfn = zero, lpn = zero, rpf_k = zero;
         if (oc) {
-            const double kw = sh.kc[ty][tx - 1], ke = sh.kc[ty][tx + 1];
-            const double ks = sh.kc[ty - 1][tx], kn = sh.kc[ty + 1][tx];
-            const double qxl = (i >= 1) ? -0.5 * (kw + kc_c) * (pf_c - sh.pf[ty][tx - 1]) * c.dxi : 0.0;
-            const double qxh = (i + 1 < g.nx) ? -0.5 * (kc_c + ke) * (sh.pf[ty][tx + 1] - pf_c) * c.dxi : 0.0;
-            const double qyl = (j >= 1) ? -0.5 * (ks + kc_c) * (pf_c - sh.pf[ty - 1][tx]) * c.dyi : 0.0;
-            const double qyh = (j + 1 < g.ny) ? -0.5 * (kc_c + kn) * (sh.pf[ty + 1][tx] - pf_c) * c.dyi : 0.0;
-            const double qzl = (pz >= 1) ? -0.5 * (kc_p + kc_c) * ((pf_c - pf_p) * c.dzi + c.buoy) : 0.0;
-            const double qzh = pln ? -0.5 * (kc_c + kc_n) * ((pf_n - pf_c) * c.dzi + c.buoy) : 0.0;
-            const double divq = (qxh - qxl) * c.dxi + (qyh - qyl) * c.dyi + (qzh - qzl) * c.dzi;
-            double kl = kc_c;
+            const T buoy = CORR ? zero : c.buoy;
+            const T kw = sh.kc[ty][tx - 1], ke = sh.kc[ty][tx + 1];
+            const T ks = sh.kc[ty - 1][tx], kn = sh.kc[ty + 1][tx];
+            const T qxl = (i >= 1) ? -half * (kw + kc_c) * (pf_c - sh.pf[ty][tx - 1]) * c.dxi : zero;
+            const T qxh = (i + 1 < g.nx) ? -half * (kc_c + ke) * (sh.pf[ty][tx + 1] - pf_c) * c.dxi : zero;
+            const T qyl = (j >= 1) ? -half * (ks + kc_c) * (pf_c - sh.pf[ty - 1][tx]) * c.dyi : zero;
+            const T qyh = (j + 1 < g.ny) ? -half * (kc_c + kn) * (sh.pf[ty + 1][tx] - pf_c) * c.dyi : zero;
+            const T qzl = (pz >= 1) ? -half * (kc_p + kc_c) * ((pf_c - pf_p) * c.dzi + buoy) : zero;
+            const T qzh = pln ? -half * (kc_c + kc_n) * ((pf_n - pf_c) * c.dzi + buoy) : zero;
+            const T divq = (qxh - qxl) * c.dxi + (qyh - qyl) * c.dyi + (qzh - qzl) * c.dzi;
+            T kl = kc_c;
             if (i >= 1) kl = fmax(kl, kw);
             if (i + 1 < g.nx) kl = fmax(kl, ke);
             if (j >= 1) kl = fmax(kl, ks);
             if (j + 1 < g.ny) kl = fmax(kl, kn);
             if (pz >= 1) kl = fmax(kl, kc_p);
             if (pln) kl = fmax(kl, kc_n);
-            const double dtf = c.dtaupf_c / kl;
-            pfn = (pf_c - dtf * (divq + c.beta_d * (-c.ab * pfo - c.alpha * (pt - pto)) * c.dti - pt * chi)) /
-                  (1.0 + dtf * (c.beta_d * c.ab * c.dti + chi));
-            if (NORMS)
+            const T dtf = c.dtaupf_c / kl;
+            if constexpr (CORR) {
+                pfn = (pf_c - dtf * (divq + pfo - c.beta_d * c.alpha * pt * c.dti - pt * chi)) /
+                      (one + dtf * (c.beta_d * c.ab * c.dti + chi));
+                if (WNORM) rpf_k = pfo + divq + c.beta_d * (c.ab * pf_c - c.alpha * pt) * c.dti + (pf_c - pt) * chi;
+            } else if constexpr (RESID) {
+                pfn = pf_c;
                 rpf_k = divq + c.beta_d * (c.ab * (pf_c - pfo) - c.alpha * (pt - pto)) * c.dti + (pf_c - pt) * chi;
-            if (UPD_LP) {
-                double adv = 0.5 * vx_c * (s_c - sh.s[ty][tx - 1]) * c.dxi;
-                adv += 0.5 * sh.vx[ty][tx + 1] * (sh.s[ty][tx + 1] - s_c) * c.dxi;
-                adv += 0.5 * vy_c * (s_c - sh.s[ty - 1][tx]) * c.dyi;
-                adv += 0.5 * sh.vy[ty + 1][tx] * (sh.s[ty + 1][tx] - s_c) * c.dyi;
-                adv += 0.5 * vz_c * (s_c - s_p) * c.dzi;
-                adv += 0.5 * vz_n * (s_n - s_c) * c.dzi;
-                const double dphidt = c.beta_phi * ((pfn - pfo) - (ptn - pto)) * c.dti + (pfn - ptn) / eta + adv;
+            } else {
+                pfn = (pf_c - dtf * (divq + c.beta_d * (-c.ab * pfo - c.alpha * (pt - pto)) * c.dti - pt * chi)) /
+                      (one + dtf * (c.beta_d * c.ab * c.dti + chi));
+                if (WNORM)
+                    rpf_k = divq + c.beta_d * (c.ab * (pf_c - pfo) - c.alpha * (pt - pto)) * c.dti + (pf_c - pt) * chi;
+            }
+            if constexpr (UPD_LP) {
+                T adv = half * vx_c * (s_c - sh.s[ty][tx - 1]) * c.dxi;
+                adv += half * sh.vx[ty][tx + 1] * (sh.s[ty][tx + 1] - s_c) * c.dxi;
+                adv += half * vy_c * (s_c - sh.s[ty - 1][tx]) * c.dyi;
+                adv += half * sh.vy[ty + 1][tx] * (sh.s[ty + 1][tx] - s_c) * c.dyi;
+                adv += half * vz_c * (s_c - s_p) * c.dzi;
+                adv += half * vz_n * (s_n - s_c) * c.dzi;
+                const T dphidt = c.beta_phi * ((pfn - pfo) - (ptn - pto)) * c.dti + (pfn - ptn) / eta + adv;
                 lpn = lpo - c.dt * dphidt;
             }
         }
 
         // ---- shear stresses on the xy-edges of plane pz and the xz/yz-edges of level pz+1 ----
-        double txz_n = 0.0, tyz_n = 0.0, txy = 0.0;
+        T txz_n = zero, tyz_n = zero, txy = zero;
         if (edge) {
             if (plc && i >= 1 && i < g.nx && j >= 1 && j < g.ny) {
-                const double mue = 0.25 * (sh.mu[ty - 1][tx - 1] + sh.mu[ty - 1][tx] + sh.mu[ty][tx - 1] + mu_c);
-                const double xie = mue * c.gdts_inv;
-                const double be = 2.0 * mue / (1.0 + xie);
-                const double exy = 0.5 * ((vx_c - sh.vx[ty - 1][tx]) * c.dyi + (vy_c - sh.vy[ty][tx - 1]) * c.dxi);
+                const T mue = quarter * (sh.mu[ty - 1][tx - 1] + sh.mu[ty - 1][tx] + sh.mu[ty][tx - 1] + mu_c);
+                const T xie = mue * c.gdts_inv;
+                const T be = two * mue / (one + xie);
+                const T exy = half * ((vx_c - sh.vx[ty - 1][tx]) * c.dyi + (vy_c - sh.vy[ty][tx - 1]) * c.dxi);
                 txy = be * exy;
             }
             const bool lev = (pz + 1 >= 1) && (pz + 1 < g.nz);
             if (lev && i >= 1 && i < g.nx && cj) {
-                const double mue = 0.25 * (sh.mu[ty][tx - 1] + mu_c + sh.mu1[ty][tx - 1] + mu_n);
-                const double xie = mue * c.gdts_inv;
-                const double be = 2.0 * mue / (1.0 + xie);
-                const double exz = 0.5 * ((vx_n - vx_c) * c.dzi + (vz_n - sh.vz1[ty][tx - 1]) * c.dxi);
+                const T mue = quarter * (sh.mu[ty][tx - 1] + mu_c + sh.mu1[ty][tx - 1] + mu_n);
+                const T xie = mue * c.gdts_inv;
+                const T be = two * mue / (one + xie);
+                const T exz = half * ((vx_n - vx_c) * c.dzi + (vz_n - sh.vz1[ty][tx - 1]) * c.dxi);
                 txz_n = be * exz;
             }
             if (lev && j >= 1 && j < g.ny && ci) {
-                const double mue = 0.25 * (sh.mu[ty - 1][tx] + mu_c + sh.mu1[ty - 1][tx] + mu_n);
-                const double xie = mue * c.gdts_inv;
-                const double be = 2.0 * mue / (1.0 + xie);
-                const double eyz = 0.5 * ((vy_n - vy_c) * c.dzi + (vz_n - sh.vz1[ty - 1][tx]) * c.dyi);
+                const T mue = quarter * (sh.mu[ty - 1][tx] + mu_c + sh.mu1[ty - 1][tx] + mu_n);
+                const T xie = mue * c.gdts_inv;
+                const T be = two * mue / (one + xie);
+                const T eyz = half * ((vy_n - vy_c) * c.dzi + (vz_n - sh.vz1[ty - 1][tx]) * c.dyi);
                 tyz_n = be * eyz;
             }
         }
@@ -274,54 +328,80 @@ __global__ __launch_bounds__(BX * BY) void k_iter(Geom g, Coef c, IterPtrs p) {
         if (oc) {
             const int64_t o = (int64_t)pz * g.S + col;
             if (i >= 1) {
-                const double f = (txx - sh.txx[ty][tx - 1]) * c.dxi + (sh.txy[ty + 1][tx] - txy) * c.dyi +
-                                 (txz_n - txz_c) * c.dzi - (ptn - sh.ptn[ty][tx - 1]) * c.dxi + fox;
-                double r = f * c.rho_i_inv + c.dampx * rx;
-                double v = vx_c + (c.dtauv_c / fmax(mu_c, sh.mu[ty][tx - 1])) * r;
-                if (c.mech_off) { r = rx; v = vx_c; }
-                p.rx_o[o] = r;
-                p.vx_o[o] = v;
-                if (NORMS) {
-                    nm[0] = nanmax(nm[0], fabs(f - (w - sh.w[ty][tx - 1]) * c.dxi));
-                    nm[7] = nanmax(nm[7], fabs(v - vx_c));
+                const T f = (txx - sh.txx[ty][tx - 1]) * c.dxi + (sh.txy[ty + 1][tx] - txy) * c.dyi +
+                            (txz_n - txz_c) * c.dzi - (ptn - sh.ptn[ty][tx - 1]) * c.dxi + fox;
+                if constexpr (RESID) {
+                    p.res_fx[o] = float(f);
+                    nm[0] = nanmax(nm[0], T(fabs(f)));
+                } else {
+                    T r = f * c.rho_i_inv + c.dampx * rx;
+                    T v = vx_c + (c.dtauv_c / fmax(mu_c, sh.mu[ty][tx - 1])) * r;
+                    if (c.mech_off) { r = rx; v = vx_c; }
+                    p.rx_o[o] = r;
+                    p.vx_o[o] = v;
+                    if (NORMS) {
+                        nm[0] = nanmax(nm[0], T(fabs(f - (w - sh.w[ty][tx - 1]) * c.dxi)));
+                        nm[7] = nanmax(nm[7], T(fabs(v - vx_c)));
+                    }
                 }
             }
             if (j >= 1) {
-                const double f = (sh.txy[ty][tx + 1] - txy) * c.dxi + (tyy - sh.tyy[ty - 1][tx]) * c.dyi +
-                                 (tyz_n - tyz_c) * c.dzi - (ptn - sh.ptn[ty - 1][tx]) * c.dyi + foy;
-                double r = f * c.rho_i_inv + c.dampy * ry;
-                double v = vy_c + (c.dtauv_c / fmax(mu_c, sh.mu[ty - 1][tx])) * r;
-                if (c.mech_off) { r = ry; v = vy_c; }
-                p.ry_o[o] = r;
-                p.vy_o[o] = v;
-                if (NORMS) {
-                    nm[0] = nanmax(nm[0], fabs(f - (w - sh.w[ty - 1][tx]) * c.dyi));
-                    nm[7] = nanmax(nm[7], fabs(v - vy_c));
+                const T f = (sh.txy[ty][tx + 1] - txy) * c.dxi + (tyy - sh.tyy[ty - 1][tx]) * c.dyi +
+                            (tyz_n - tyz_c) * c.dzi - (ptn - sh.ptn[ty - 1][tx]) * c.dyi + foy;
+                if constexpr (RESID) {
+                    p.res_fy[o] = float(f);
+                    nm[0] = nanmax(nm[0], T(fabs(f)));
+                } else {
+                    T r = f * c.rho_i_inv + c.dampy * ry;
+                    T v = vy_c + (c.dtauv_c / fmax(mu_c, sh.mu[ty - 1][tx])) * r;
+                    if (c.mech_off) { r = ry; v = vy_c; }
+                    p.ry_o[o] = r;
+                    p.vy_o[o] = v;
+                    if (NORMS) {
+                        nm[0] = nanmax(nm[0], T(fabs(f - (w - sh.w[ty - 1][tx]) * c.dyi)));
+                        nm[7] = nanmax(nm[7], T(fabs(v - vy_c)));
+                    }
                 }
             }
             if (pz >= 1) {
-                const double f = (sh.txz[bc][ty][tx + 1] - txz_c) * c.dxi + (sh.tyz[bc][ty + 1][tx] - tyz_c) * c.dyi +
-                                 (tzz - tzz_p) * c.dzi - (ptn - ptn_p) * c.dzi - (0.5 * (rg_p + rg) - c.rhobg) + foz;
-                double r = f * c.rho_i_inv + c.dampz * rz;
-                double v = vz_c + (c.dtauv_c / fmax(mu_c, mu_p)) * r;
-                if (c.mech_off) { r = rz; v = vz_c; }
-                p.rz_o[o] = r;
-                p.vz_o[o] = v;
-                if (NORMS) {
-                    nm[0] = nanmax(nm[0], fabs(f - (w - w_p) * c.dzi));
-                    nm[6] = nanmax(nm[6], fabs(v - vz_c));
-                    nm[7] = nanmax(nm[7], fabs(v - vz_c));
+                const T fs = (sh.txz[bc][ty][tx + 1] - txz_c) * c.dxi + (sh.tyz[bc][ty + 1][tx] - tyz_c) * c.dyi +
+                             (tzz - tzz_p) * c.dzi - (ptn - ptn_p) * c.dzi;
+                T f;
+                if constexpr (CORR) {
+                    f = fs + foz;
+                } else {
+                    f = fs - (half * (rg_p + rg) - c.rhobg) + foz;
+                }
+                if constexpr (RESID) {
+                    p.res_fz[o] = float(f);
+                    nm[0] = nanmax(nm[0], T(fabs(f)));
+                } else {
+                    T r = f * c.rho_i_inv + c.dampz * rz;
+                    T v = vz_c + (c.dtauv_c / fmax(mu_c, mu_p)) * r;
+                    if (c.mech_off) { r = rz; v = vz_c; }
+                    p.rz_o[o] = r;
+                    p.vz_o[o] = v;
+                    if (NORMS) {
+                        nm[0] = nanmax(nm[0], T(fabs(f - (w - w_p) * c.dzi)));
+                        nm[6] = nanmax(nm[6], T(fabs(v - vz_c)));
+                        nm[7] = nanmax(nm[7], T(fabs(v - vz_c)));
+                    }
                 }
             }
-            p.pt_o[o] = ptn;
-            p.pf_o[o] = pfn;
-            if (UPD_LP) p.lp_o[o] = lpn;
-            if (NORMS) {
-                nm[1] = nanmax(nm[1], fabs(rpt_k));
-                nm[2] = nanmax(nm[2], fabs(rpf_k));
-                if (UPD_LP) nm[3] = nanmax(nm[3], fabs(lpn - lp_c));
-                nm[4] = nanmax(nm[4], fabs(ptn - pt));
-                nm[5] = nanmax(nm[5], fabs(pfn - pf_c));
+            if constexpr (RESID) {
+                p.res_rpt[o] = float(rpt_k);
+                p.res_rpf[o] = float(rpf_k);
+            } else {
+                p.pt_o[o] = ptn;
+                p.pf_o[o] = pfn;
+                if (UPD_LP) p.lp_o[o] = lpn;
+            }
+            if (WNORM) {
+                nm[1] = nanmax(nm[1], T(fabs(rpt_k)));
+                nm[2] = nanmax(nm[2], T(fabs(rpf_k)));
+                if (UPD_LP) nm[3] = nanmax(nm[3], T(fabs(lpn - lp_c)));
+                nm[4] = nanmax(nm[4], T(fabs(ptn - pt)));
+                nm[5] = nanmax(nm[5], T(fabs(pfn - pf_c)));
             }
         }
 
@@ -338,20 +418,20 @@ __global__ __launch_bounds__(BX * BY) void k_iter(Geom g, Coef c, IterPtrs p) {
         cc = cn;
     }
 
-    if (NORMS) {
+    if (WNORM) {
         // block maximum: wave64 butterfly, then across the waves through LDS
         __shared__ double red[(BX * BY) / 64][NNORM];
 #pragma unroll
         for (int q = 0; q < NNORM; ++q) {
-            double v = nm[q];
-            for (int off = 32; off >= 1; off >>= 1) v = nanmax(v, __shfl_xor(v, off, 64));
+            T v = nm[q];
+            for (int off = 32; off >= 1; off >>= 1) v = nanmax(v, T(__shfl_xor(v, off, 64)));
             nm[q] = v;
         }
         const int lin = ty * BX + tx;
         const int wave = lin >> 6, lane = lin & 63;
         if (lane == 0) {
 #pragma unroll
-            for (int q = 0; q < NNORM; ++q) red[wave][q] = nm[q];
+            for (int q = 0; q < NNORM; ++q) red[wave][q] = double(nm[q]);
         }
         __syncthreads();
         if (lin < NNORM) {
@@ -393,17 +473,33 @@ __global__ __launch_bounds__(256) void k_reduce_max(const double* __restrict__ p
 
 }  // namespace
 
-hipError_t launch_iteration(const Geom& g, const Coef& c, const IterPtrs& p, int update_lp, int norms,
+hipError_t launch_iteration(const Geom& g, const Coef& c, const SweepPtrs<double>& p, int mode, int norms,
                             hipStream_t s) {
     const dim3 block(BX, BY, 1);
     const dim3 grid((unsigned)iter_grid_blocks(g), 1, 1);
-    if (update_lp) {
-        if (norms) hipLaunchKernelGGL((k_iter<true, true>), grid, block, 0, s, g, c, p);
-        else hipLaunchKernelGGL((k_iter<true, false>), grid, block, 0, s, g, c, p);
-    } else {
-        if (norms) hipLaunchKernelGGL((k_iter<false, true>), grid, block, 0, s, g, c, p);
-        else hipLaunchKernelGGL((k_iter<false, false>), grid, block, 0, s, g, c, p);
+    switch (mode) {
+        case MD_THESIS:
+            if (norms) hipLaunchKernelGGL((k_sweep<double, MD_THESIS, true>), grid, block, 0, s, g, c, p);
+            else hipLaunchKernelGGL((k_sweep<double, MD_THESIS, false>), grid, block, 0, s, g, c, p);
+            break;
+        case MD_LINEAR:
+            if (norms) hipLaunchKernelGGL((k_sweep<double, MD_LINEAR, true>), grid, block, 0, s, g, c, p);
+            else hipLaunchKernelGGL((k_sweep<double, MD_LINEAR, false>), grid, block, 0, s, g, c, p);
+            break;
+        case MD_RESID:
+            hipLaunchKernelGGL((k_sweep<double, MD_RESID, false>), grid, block, 0, s, g, c, p);
+            break;
+        default:
+            return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_correction(const Geom& g, const Coef& c, const SweepPtrs<float>& p, int norms, hipStream_t s) {
+    const dim3 block(BX, BY, 1);
+    const dim3 grid((unsigned)iter_grid_blocks(g), 1, 1);
+    if (norms) hipLaunchKernelGGL((k_sweep<float, MD_CORR, true>), grid, block, 0, s, g, c, p);
+    else hipLaunchKernelGGL((k_sweep<float, MD_CORR, false>), grid, block, 0, s, g, c, p);
     return hipGetLastError();
 }
 

@@ -13,6 +13,7 @@ struct Geom {
     int nx, ny, nz;
     int64_t P;   // row pitch (elements)
     int64_t S;   // plane pitch = (ny + 1) * P
+    int kz;      // planes per z chunk of the sweep (chosen at create time)
 };
 
 // Physical and numerical constants, in the form the kernels use them.
@@ -35,12 +36,23 @@ struct Coef {
     int mech_off;
 };
 
-// Pointers of one PT sweep (inputs at iteration k, outputs at k + 1).
-struct IterPtrs {
-    const double *vx, *vy, *vz, *pt, *pf, *lp, *rx, *ry, *rz;
-    const double *fox, *foy, *foz, *pto, *pfo, *lpo, *kc, *eta, *mus;
-    double *vx_o, *vy_o, *vz_o, *pt_o, *pf_o, *lp_o, *rx_o, *ry_o, *rz_o;
-    double* partials;              // [n_blocks][8] maxima (norm variant)
+// Sweep modes (see iter_kernel.hip).
+constexpr int MD_THESIS = 0;   // FP64, porosity updated
+constexpr int MD_LINEAR = 1;   // FP64, porosity frozen
+constexpr int MD_RESID = 2;    // FP64, residuals of the present state only
+constexpr int MD_CORR = 3;     // FP32 correction sweep
+
+// Pointers of one sweep (inputs at iteration k, outputs at k + 1).  In the
+// correction mode the slots carry: vx..rz = correction d and its damped
+// residual; pto = r_Pt(x), pfo = r_Pf(x), fox..foz = momentum residual f(x);
+// eta = 1/((1-phi) eta_phi); kc, mus = FP32 copies of the coefficients.
+template <typename T>
+struct SweepPtrs {
+    const T *vx, *vy, *vz, *pt, *pf, *lp, *rx, *ry, *rz;
+    const T *fox, *foy, *foz, *pto, *pfo, *lpo, *kc, *eta, *mus;
+    T *vx_o, *vy_o, *vz_o, *pt_o, *pf_o, *lp_o, *rx_o, *ry_o, *rz_o;
+    float *res_fx, *res_fy, *res_fz, *res_rpt, *res_rpf;   // residual mode outputs
+    double* partials;              // [n_blocks][8] maxima (norm variants)
 };
 
 constexpr int NNORM = 8;
@@ -49,18 +61,29 @@ constexpr int NNORM = 8;
 // output tile plus one halo column/row on every side and marches in z.
 constexpr int BX = 64;
 constexpr int BY = 8;
-constexpr int KZ = 64;
+constexpr int KZ_MAX = 64;
+
+inline int64_t tiles_xy(const Geom& g) {
+    return (int64_t)((g.nx + BX - 3) / (BX - 2)) * ((g.ny + BY - 3) / (BY - 2));
+}
 
 inline int64_t iter_grid_blocks(const Geom& g) {
-    int64_t gx = (g.nx + BX - 3) / (BX - 2);
-    int64_t gy = (g.ny + BY - 3) / (BY - 2);
-    int64_t gz = (g.nz + KZ - 1) / KZ;
-    return gx * gy * gz;
+    return tiles_xy(g) * ((g.nz + g.kz - 1) / g.kz);
+}
+
+// Longest z chunk that still gives the 256 CUs a few blocks each (short
+// chunks cost one extra halo plane per chunk).
+inline int choose_kz(const Geom& g) {
+    int kz = KZ_MAX;
+    while (kz > 8 && tiles_xy(g) * ((g.nz + kz - 1) / kz) < 1536) kz /= 2;
+    return kz;
 }
 
 // Launchers (defined in the .hip files).
-hipError_t launch_iteration(const Geom& g, const Coef& c, const IterPtrs& p, int update_lp,
+hipError_t launch_iteration(const Geom& g, const Coef& c, const SweepPtrs<double>& p, int mode,
                             int norms, hipStream_t s);
+hipError_t launch_correction(const Geom& g, const Coef& c, const SweepPtrs<float>& p, int norms,
+                             hipStream_t s);
 hipError_t launch_reduce_max(const double* partials, int64_t nblocks, double* out8, hipStream_t s);
 
 struct AuxPtrs {
@@ -90,5 +113,17 @@ hipError_t launch_fo(const Geom& g, const Coef& c, const RefreshCoef& r, const A
                      hipStream_t s);
 hipError_t launch_porosity_step(const Geom& g, const Coef& c, const AuxPtrs& a, hipStream_t s);
 hipError_t launch_copy(const double* src, double* dst, int64_t n, hipStream_t s);
+
+// Mixed precision helpers.
+struct MixedPtrs {
+    // FP64 state (present copies) and coefficients
+    double *vx, *vy, *vz, *pt, *pf;
+    const double *lp, *kc, *eta, *mus;
+    // FP32 correction (present copies) and coefficient copies
+    const float *dvx, *dvy, *dvz, *dpt, *dpf;
+    float *kc32, *mus32, *chi32;
+};
+hipError_t launch_prepare_mixed(const Geom& g, const MixedPtrs& m, hipStream_t s);
+hipError_t launch_apply_correction(const Geom& g, const MixedPtrs& m, hipStream_t s);
 
 }  // namespace ptk

@@ -171,6 +171,46 @@ class Grid:
     def porosity_step(self):
         _check(self.lib, self.h, self.lib.pt_porosity_step(self.h), "porosity_step")
 
+    # ---- mixed precision ----------------------------------------------------
+    def enable_mixed(self):
+        """Allocate and bind the FP32 workspace of the defect-correction solve."""
+        if getattr(self, "mws", None) is not None:
+            return
+        nbytes = C.c_size_t()
+        _check(self.lib, self.h, self.lib.pt_mixed_workspace_size(self.h, C.byref(nbytes)), "mixed size")
+        with torch.cuda.stream(self.stream):
+            self.mws = torch.zeros((nbytes.value + 3) // 4, dtype=torch.float32, device=self.device)
+        _check(self.lib, self.h, self.lib.pt_bind_mixed_workspace(self.h, C.c_void_p(self.mws.data_ptr()),
+                                                                  nbytes.value), "bind mixed")
+
+    def residual(self):
+        """FP64 residual norms of the present state (see pt_residual)."""
+        self.enable_mixed()
+        _check(self.lib, self.h, self.lib.pt_residual(self.h), "residual")
+        return self.last_norms()
+
+    def residual_fields(self):
+        """(fx, fy, fz, r_Pt, r_Pf) last written by residual(), as numpy."""
+        box = (self.nz + 1) * (self.ny + 1) * self.pitch
+        out = []
+        for b, name in enumerate(("vx", "vy", "vz", "pt", "pf")):
+            t = self.mws[(16 + b) * box:(17 + b) * box].view(self.nz + 1, self.ny + 1, self.pitch)
+            ez, ey, ex = field_extent(name, self.nx, self.ny, self.nz)
+            with torch.cuda.stream(self.stream):
+                out.append(t[:ez, :ey, :ex].double().cpu().numpy())
+        return out
+
+    def solve_mixed(self, rtol, eta_in=1e-4, max_inner=1_000_000, max_outer=50):
+        """Defect-correction solve of the present Picard stage (see pt_solve_mixed)."""
+        self.enable_mixed()
+        inner = C.c_int64()
+        outer = C.c_int32()
+        rho = C.c_double()
+        st = _check(self.lib, self.h, self.lib.pt_solve_mixed(self.h, float(rtol), float(eta_in), int(max_inner),
+                                                               int(max_outer), C.byref(inner), C.byref(outer),
+                                                               C.byref(rho)), "solve_mixed")
+        return inner.value, outer.value, rho.value, st == 0
+
     def copy(self, src: torch.Tensor, dst: torch.Tensor):
         assert src.dtype == dst.dtype == torch.float64 and src.numel() == dst.numel()
         _check(self.lib, self.h, self.lib.pt_copy(self.h, C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()),

@@ -18,7 +18,6 @@ Conventions
 from __future__ import annotations
 
 import dataclasses
-import math
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -152,7 +151,7 @@ def gaussian_random_field(shape, lengths, corr: float, seed: int) -> np.ndarray:
     kx = np.fft.rfftfreq(big[2], d=lx / nx) * 2 * np.pi
     k2 = kz[:, None, None] ** 2 + ky[None, :, None] ** 2 + kx[None, None, :] ** 2
     filt = np.exp(-k2 * corr * corr / 8.0)
-    f = np.fft.irfftn(np.fft.rfftn(w) * filt, s=big)[:nz, :ny, :nx]
+    f = np.fft.irfftn(np.fft.rfftn(w) * filt, s=big, axes=(0, 1, 2))[:nz, :ny, :nx]
     f = f - f.mean()
     f = f / f.std()
     return np.ascontiguousarray(f)
@@ -197,6 +196,13 @@ def sensor_cells(seed: int, count: int, shape, margin: int = 1) -> np.ndarray:
 # The five workloads
 # ---------------------------------------------------------------------------
 
+# Physical step of the Picard-schedule workloads on the unit cube.  The paper
+# does not state one for these set-ups; with dt = 1e-3 the storage terms are
+# so weak against Darcy diffusion that the thesis's PT iteration needs more
+# than 6e4 iterations per linear solve already at 16^3, while 1e-5 keeps it in
+# the storage-dominated regime the thesis runs in.
+PICARD_DT = 1e-5
+
 def config_parity(n: int = 32, seed: int = 1) -> Config:
     """FP64 parity workload: unit cube, one Gaussian anomaly of amplitude
     2*phi0 and width 0.1 at (0.5, 0.5, 0.25), +-1e-3 noise, scalar k0,
@@ -210,7 +216,8 @@ def config_fp64_picard(n: int = 255, seed: int = 2) -> Config:
     """FP64 Picard workload: parity recipe plus lognormal (sigma 0.5) k0."""
     c = config_parity(n, seed)
     return dataclasses.replace(c, name=f"picard{n}", k0_kind="lognormal",
-                               k0_seed=seed, mode="picard", n_picard=5, rtol=1e-8)
+                               k0_seed=seed, mode="picard", n_picard=5, rtol=1e-8,
+                               phys=c.phys.replace(dt=PICARD_DT, dtS=PICARD_DT))
 
 
 def config_mixed(n: int = 511, seed: int = 3) -> Config:
@@ -219,7 +226,8 @@ def config_mixed(n: int = 511, seed: int = 3) -> Config:
     Drucker-Prager cap (C = 1, 30 degrees)."""
     cen = random_centres(seed, 2, (0.3, 0.3, 0.15), (0.7, 0.7, 0.45))
     return Config(name=f"mixed{n}", nx=n, ny=n, nz=n,
-                  phys=Physics(dpcap=True, coh=1.0, fric_deg=30.0, tau_y_min=1e-3),
+                  phys=Physics(dpcap=True, coh=1.0, fric_deg=30.0, tau_y_min=1e-3,
+                               dt=PICARD_DT, dtS=PICARD_DT),
                   anomalies=[Anomaly(cen[0], 2.0, 0.1), Anomaly(cen[1], 1.5, 0.1)],
                   noise_seed=seed, k0_kind="lognormal", k0_seed=seed,
                   mode="picard", n_picard=5, rtol=1e-8)
@@ -262,13 +270,7 @@ def initial_fields(cfg: Config) -> dict:
     return {"phi": porosity_field(cfg), "k0": k0_field(cfg)}
 
 
-def teff_sizes(n: int) -> dict:
-    """Sizes that the measurement tables use (no solver arithmetic)."""
-    N = n ** 3
-    return {"n": n, "N": N, "faces": (n + 1) * n * n}
-
-
 __all__ = ["Physics", "Anomaly", "Config", "CONFIGS", "config_parity",
            "config_fp64_picard", "config_mixed", "config_adjoint", "config_waves",
            "initial_fields", "porosity_field", "k0_field", "gaussian_random_field",
-           "sensor_cells", "random_centres", "cell_centres", "math"]
+           "sensor_cells", "random_centres", "cell_centres", "PICARD_DT"]
