@@ -99,6 +99,7 @@ def time_to_tol(n: int, rtol: float = 1e-8, n_picard: int = 5, eta_in: float = 1
     torch.cuda.synchronize()
     del w
 
+    chunk, max_fp64, max_outer = 20000, 1_000_000, 40
     out = {"n": n, "rtol": rtol, "picard_stages": n_picard, "eta_in": eta_in,
            "dt": cfg.phys.dt, "workload": f"{n}^3 two-anomaly grid, lognormal k0, DP cap; one Picard step"}
     fields = {}
@@ -113,14 +114,30 @@ def time_to_tol(n: int, rtol: float = 1e-8, n_picard: int = 5, eta_in: float = 1
         ok_all = True
         for _ in range(n_picard):
             g.refresh(1.0, 1.0)
+            ts = time.perf_counter()
+            # the solves run in chunks (they resume where they stopped) so
+            # that every chunk reports its progress
             if mode == "fp64":
-                it, rho, ok = g.solve_linear(rtol, 2_000_000)
-                its.append(it)
+                total, ok = 0, False
+                while not ok and total < max_fp64:
+                    it, rho, ok = g.solve_linear(rtol, chunk)
+                    total += it
+                    print(f"time-to-tol fp64 n={n} stage {len(its) + 1}: {total} iterations rho={rho:.2e}",
+                          file=sys.stderr, flush=True)
+                its.append(total)
             else:
-                inner, outer, rho, ok = g.solve_mixed(rtol, eta_in, 2_000_000, 60)
-                its.append([inner, outer])
+                inner_t, outer_t, ok = 0, 0, False
+                while not ok and outer_t < max_outer:
+                    inner, outer, rho, ok = g.solve_mixed(rtol, eta_in, max_fp64, 1)
+                    inner_t += inner
+                    outer_t += outer
+                    print(f"time-to-tol mixed n={n} stage {len(its) + 1}: {inner_t} FP32 sweeps, "
+                          f"{outer_t} corrections rho={rho:.2e}", file=sys.stderr, flush=True)
+                its.append([inner_t, outer_t])
             ok_all = ok_all and ok
             g.porosity_step()
+            print(f"time-to-tol {mode} n={n} stage {len(its)} done in {time.perf_counter() - ts:.2f} s",
+                  file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         out[f"{mode}_s"] = round(time.perf_counter() - t0, 3)
         out[f"{mode}_iters"] = its

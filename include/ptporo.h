@@ -184,11 +184,20 @@ pt_status pt_last_norms(pt_grid* g, pt_norms* out);
 
 /* Linear PT solve with coefficients and porosity frozen, until
  * rho = max(g_V / g_V0, g_P / g_P0) <= rtol (g_V = max|f|,
- * g_P = max(|r_Pt|, |r_Pf|), 0 = first iteration of this solve; groups with
- * zero initial norm are dropped), checked every nup iterations, or max_iter.
- * Synchronises.  Returns PT_ENOTCONV at max_iter. */
+ * g_P = max(|r_Pt|, |r_Pf|); groups with zero reference norm are dropped),
+ * checked every nup iterations, or max_iter.  The reference (g_V0, g_P0) is
+ * the residual of the step's first solve: set by the first solve after
+ * pt_begin_step and kept for the step's later Picard stages (a later stage
+ * starts from a residual that is already small, so a stage-local reference
+ * would ask for a reduction below round-off).  Synchronises.  Returns
+ * PT_ENOTCONV at max_iter (the state is valid; calling again continues). */
 pt_status pt_solve_linear(pt_grid* g, double rtol, int64_t max_iter,
                           int64_t* iters, double* rho);
+
+/* The residual reference of the current step (both -1 if not yet set), and
+ * setting it explicitly (negative values unset it). */
+pt_status pt_residual_reference(const pt_grid* g, double* gv, double* gp);
+pt_status pt_set_residual_reference(pt_grid* g, double gv, double gp);
 
 /* Porosity time step after a converged Picard stage: ln(1-phi) =
  * ln(1-phi)o - dt dphi/dt(V, Pt, Pf) (eq (22)) with the present solid
@@ -210,10 +219,12 @@ pt_status pt_residual(pt_grid* g);
 
 /* One linear Picard stage solved by defect correction (coefficients and
  * porosity frozen, as pt_solve_linear): repeat { r = residual of x in FP64;
- * stop when rho = max(g_V/g_V0, g_P/g_P0) <= rtol; solve A d = -r by FP32 PT
- * sweeps from d = 0 until the correction residual falls to eta_in times r
- * (checked every nup sweeps) or max_inner sweeps; x += d in FP64 }.  At most
- * max_outer corrections.  Synchronises.  PT_ENOTCONV if rtol is not met. */
+ * stop when rho (as in pt_solve_linear, same step reference) <= rtol; solve
+ * A d = -r by FP32 PT sweeps from d = 0 until the correction residual falls
+ * to eta_in times r, stops improving (no new 1 % minimum in 40 checks: the
+ * FP32 round-off floor) or max_inner sweeps, checked every nup sweeps;
+ * x += d in FP64 }.  At most max_outer corrections.  Synchronises.
+ * PT_ENOTCONV if rtol is not met (calling again continues). */
 pt_status pt_solve_mixed(pt_grid* g, double rtol, double eta_in, int64_t max_inner, int32_t max_outer,
                          int64_t* inner_iters, int32_t* outer_iters, double* rho);
 

@@ -179,6 +179,7 @@ class Oracle:
         """Old values; stress history from the current state from step 2 on."""
         self.lib.or_begin_step(self.ctx, C.byref(self._st), int(self.step_index >= 1))
         self.iter = 0
+        self.ref = None        # residual reference of the step, set by its first solve
 
     def end_step(self):
         self.step_index += 1
@@ -249,21 +250,24 @@ class Oracle:
     def solve_linear(self, rtol, max_iter=200000):
         """PT iterations with porosity and coefficients frozen until
         rho = max(g_V/g_V0, g_P/g_P0) <= rtol, checked every nup iterations;
-        g_V = max|f|, g_P = max(|r_Pt|, |r_Pf|), 0 = first iteration."""
+        g_V = max|f|, g_P = max(|r_Pt|, |r_Pf|); 0 = the residual at the first
+        iteration of the step's first solve (kept for its later Picard
+        stages, whose own initial residuals are already small)."""
         nup = self.phys.nup
-        g0 = None
         it = 0
         rho = np.inf
+        if not hasattr(self, "ref"):
+            self.ref = None
         while it < max_iter:
             it += 1
-            want = (it == 1) or (it % nup == 0)
+            want = (it == 1 and self.ref is None) or (it % nup == 0)
             nm = self.iteration(update_lp=False, norms=want)
             if nm is None:
                 continue
             gv, gp = nm["f"], max(nm["rpt"], nm["rpf"])
-            if g0 is None:
-                g0 = (gv, gp)
-            rho = rel_residual(gv, gp, g0)
+            if self.ref is None:
+                self.ref = (gv, gp)
+            rho = rel_residual(gv, gp, self.ref)
             if it % nup == 0 and rho <= rtol:
                 break
         return it, rho

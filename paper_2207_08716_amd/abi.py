@@ -44,6 +44,7 @@ class Norms(C.Structure):
 EXPORTS = ["pt_create", "pt_destroy", "pt_field_elems", "pt_bind_field", "pt_workspace_size",
            "pt_bind_workspace", "pt_set_stream", "pt_set_params", "pt_current", "pt_begin_step",
            "pt_refresh", "pt_iteration", "pt_iterate", "pt_last_norms", "pt_solve_linear",
+           "pt_residual_reference", "pt_set_residual_reference",
            "pt_porosity_step", "pt_mixed_workspace_size", "pt_bind_mixed_workspace", "pt_residual",
            "pt_solve_mixed", "pt_copy", "pt_status_str", "pt_last_error", "pt_abi_version"]
 
@@ -83,6 +84,8 @@ def load(path: str = LIB_PATH):
     lib.pt_last_norms.argtypes = [vp, P(Norms)]
     lib.pt_solve_linear.argtypes = [vp, C.c_double, C.c_int64, P(C.c_int64), P(C.c_double)]
     lib.pt_porosity_step.argtypes = [vp]
+    lib.pt_residual_reference.argtypes = [vp, P(C.c_double), P(C.c_double)]
+    lib.pt_set_residual_reference.argtypes = [vp, C.c_double, C.c_double]
     lib.pt_copy.argtypes = [vp, vp, vp, C.c_int64]
     lib.pt_mixed_workspace_size.argtypes = [vp, P(C.c_size_t)]
     lib.pt_bind_mixed_workspace.argtypes = [vp, vp, C.c_size_t]

@@ -22,6 +22,8 @@ struct pt_grid {
     bool mws_clean = false;    // both correction copies zeroed once
     hipStream_t stream = nullptr;
     int64_t iter = 0;          // iteration count within the current step
+    double ref_v = 0.0, ref_p = 0.0;   // residual reference of the step (g_V0, g_P0)
+    bool ref_set = false;
     bool refreshed = false;    // any refresh done on this handle
     bool norms_pending = false;
     std::string err;
@@ -366,6 +368,26 @@ pt_status pt_begin_step(pt_grid* g, int32_t update_history) {
         if (e != hipSuccess) return hip_fail(g, e, "fo");
     }
     g->iter = 0;
+    g->ref_set = false;
+    return PT_OK;
+}
+
+pt_status pt_residual_reference(const pt_grid* g, double* gv, double* gp) {
+    if (!g || !gv || !gp) return PT_EINVAL;
+    *gv = g->ref_set ? g->ref_v : -1.0;
+    *gp = g->ref_set ? g->ref_p : -1.0;
+    return PT_OK;
+}
+
+pt_status pt_set_residual_reference(pt_grid* g, double gv, double gp) {
+    if (!g) return PT_EINVAL;
+    if (gv < 0.0 || gp < 0.0) {
+        g->ref_set = false;
+        return PT_OK;
+    }
+    g->ref_v = gv;
+    g->ref_p = gp;
+    g->ref_set = true;
     return PT_OK;
 }
 
@@ -415,11 +437,11 @@ pt_status pt_solve_linear(pt_grid* g, double rtol, int64_t max_iter, int64_t* it
     if (st != PT_OK) return st;
     if (!g->ws || g->ws_bytes < ws_needed(g)) return fail(g, PT_EINVAL, "workspace not bound");
     const int64_t nup = g->prm.nup;
-    double g0v = 0.0, g0p = 0.0, r = INFINITY;
+    double r = INFINITY;
     int64_t it = 0;
     while (it < max_iter) {
         ++it;
-        const bool want = (it == 1) || (it % nup == 0);
+        const bool want = (it == 1 && !g->ref_set) || (it % nup == 0);
         st = iteration_impl(g, 0, want ? 1 : 0);
         if (st != PT_OK) return st;
         if (!want) continue;
@@ -430,13 +452,14 @@ pt_status pt_solve_linear(pt_grid* g, double rtol, int64_t max_iter, int64_t* it
             return st;
         }
         const double gv = nm.f, gp = std::fmax(nm.rpt, nm.rpf);
-        if (it == 1) {
-            g0v = gv;
-            g0p = gp;
+        if (!g->ref_set) {
+            g->ref_v = gv;
+            g->ref_p = gp;
+            g->ref_set = true;
         }
         r = 0.0;
-        if (g0v > 0.0) r = std::fmax(r, gv / g0v);
-        if (g0p > 0.0) r = std::fmax(r, gp / g0p);
+        if (g->ref_v > 0.0) r = std::fmax(r, gv / g->ref_v);
+        if (g->ref_p > 0.0) r = std::fmax(r, gp / g->ref_p);
         if (it % nup == 0 && r <= rtol) break;
     }
     if (iters) *iters = it;
@@ -547,7 +570,10 @@ pt_status pt_solve_mixed(pt_grid* g, double rtol, double eta_in, int64_t max_inn
     e = launch_prepare_mixed(g->geom, mixed_ptrs(g, 0), g->stream);
     if (e != hipSuccess) return hip_fail(g, e, "prepare mixed");
     const int64_t nup = g->prm.nup;
-    double g0v = 0.0, g0p = 0.0, r = INFINITY;
+    // the inner solve stops when its residual has not reached a new minimum
+    // (by 1 %) for this many checks: FP32 cannot go below its round-off level
+    const int stall_checks = 40;
+    double r = INFINITY;
     int64_t inner_total = 0;
     int32_t outer = 0;
     for (;;) {
@@ -556,17 +582,20 @@ pt_status pt_solve_mixed(pt_grid* g, double rtol, double eta_in, int64_t max_inn
         pt_norms nm;
         st = read_norms(g, &nm);
         if (st != PT_OK) return st;
-        if (outer == 0) {
-            g0v = nm.f;
-            g0p = std::fmax(nm.rpt, nm.rpf);
+        if (!g->ref_set) {
+            g->ref_v = nm.f;
+            g->ref_p = std::fmax(nm.rpt, nm.rpf);
+            g->ref_set = true;
         }
-        r = group_rho(nm, g0v, g0p);
+        r = group_rho(nm, g->ref_v, g->ref_p);
         if (r <= rtol || outer >= max_outer) break;
         const double gv = nm.f, gp = std::fmax(nm.rpt, nm.rpf);
         // correction d = 0, damped residual 0 (copy 0 holds the present d)
         e = hipMemsetAsync(mx(g, 0), 0, 8 * box_bytes, g->stream);
         if (e != hipSuccess) return hip_fail(g, e, "correction clear");
         int cp = 0;
+        double best = INFINITY;
+        int since_best = 0;
         for (int64_t m = 1; m <= max_inner; ++m) {
             const bool chk = (m % nup == 0);
             st = correction_sweep(g, cp, chk ? 1 : 0);
@@ -577,7 +606,14 @@ pt_status pt_solve_mixed(pt_grid* g, double rtol, double eta_in, int64_t max_inn
                 pt_norms ni;
                 st = read_norms(g, &ni);
                 if (st != PT_OK) return st;
-                if (group_rho(ni, gv, gp) <= eta_in) break;
+                const double ri = group_rho(ni, gv, gp);
+                if (ri <= eta_in) break;
+                if (ri < 0.99 * best) {
+                    best = ri;
+                    since_best = 0;
+                } else if (++since_best >= stall_checks) {
+                    break;
+                }
             }
         }
         e = launch_apply_correction(g->geom, mixed_ptrs(g, cp), g->stream);

@@ -314,6 +314,12 @@ __global__ __launch_bounds__(BX * BY) void k_sweep(Geom g, Coef cd, SweepPtrs<T>
                 tyz_n = be * eyz;
             }
         }
+        // Neighbour viscosities for the velocity pseudo-steps are taken into
+        // registers now: the input planes in LDS are overwritten by the next
+        // step's staging, which faster waves may reach while the face updates
+        // below are still running.
+        const T mu_w = (tx >= 1) ? sh.mu[ty][tx - 1] : zero;
+        const T mu_s = (ty >= 1) ? sh.mu[ty - 1][tx] : zero;
         const int bn = (pz + 1) & 1, bc = pz & 1;
         sh.ptn[ty][tx] = ptn;
         sh.txx[ty][tx] = txx;
@@ -335,7 +341,7 @@ __global__ __launch_bounds__(BX * BY) void k_sweep(Geom g, Coef cd, SweepPtrs<T>
                     nm[0] = nanmax(nm[0], T(fabs(f)));
                 } else {
                     T r = f * c.rho_i_inv + c.dampx * rx;
-                    T v = vx_c + (c.dtauv_c / fmax(mu_c, sh.mu[ty][tx - 1])) * r;
+                    T v = vx_c + (c.dtauv_c / fmax(mu_c, mu_w)) * r;
                     if (c.mech_off) { r = rx; v = vx_c; }
                     p.rx_o[o] = r;
                     p.vx_o[o] = v;
@@ -353,7 +359,7 @@ __global__ __launch_bounds__(BX * BY) void k_sweep(Geom g, Coef cd, SweepPtrs<T>
                     nm[0] = nanmax(nm[0], T(fabs(f)));
                 } else {
                     T r = f * c.rho_i_inv + c.dampy * ry;
-                    T v = vy_c + (c.dtauv_c / fmax(mu_c, sh.mu[ty - 1][tx])) * r;
+                    T v = vy_c + (c.dtauv_c / fmax(mu_c, mu_s)) * r;
                     if (c.mech_off) { r = ry; v = vy_c; }
                     p.ry_o[o] = r;
                     p.vy_o[o] = v;

@@ -168,6 +168,16 @@ class Grid:
                                                                  C.byref(it), C.byref(rho)), "solve_linear")
         return it.value, rho.value, st == 0
 
+    def residual_reference(self):
+        gv = C.c_double()
+        gp = C.c_double()
+        _check(self.lib, self.h, self.lib.pt_residual_reference(self.h, C.byref(gv), C.byref(gp)), "reference")
+        return (gv.value, gp.value) if gv.value >= 0 else None
+
+    def set_residual_reference(self, ref):
+        gv, gp = ref if ref is not None else (-1.0, -1.0)
+        _check(self.lib, self.h, self.lib.pt_set_residual_reference(self.h, float(gv), float(gp)), "set reference")
+
     def porosity_step(self):
         _check(self.lib, self.h, self.lib.pt_porosity_step(self.h), "porosity_step")
 
