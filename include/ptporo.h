@@ -228,6 +228,32 @@ pt_status pt_residual(pt_grid* g);
 pt_status pt_solve_mixed(pt_grid* g, double rtol, double eta_in, int64_t max_inner, int32_t max_outer,
                          int64_t* inner_iters, int32_t* outer_iters, double* rho);
 
+/* ---- Adjoint of a linear Picard stage (gradient of a misfit) -------------
+ * Misfit J = 1/2 sum_s (Pf(cell_s) - d_s)^2 over ns distinct sensor cells,
+ * given as linear indices over the nx*ny*nz cells (x fastest).  FP64
+ * workspace: query the size for a sensor capacity, then bind. */
+pt_status pt_adjoint_workspace_size(const pt_grid* g, int32_t max_sensors, size_t* bytes);
+pt_status pt_bind_adjoint_workspace(pt_grid* g, void* dev_ptr, size_t bytes, int32_t max_sensors);
+
+/* k0 <- exp(logk0) on the cells (logk0: FP64 device buffer in the field
+ * layout).  Needs PT_F_K0FIELD. */
+pt_status pt_set_log_k0(pt_grid* g, const void* logk0_dev);
+
+/* J of the present state (host arrays sensors[ns], d_obs[ns]).  Synchronises. */
+pt_status pt_misfit(pt_grid* g, const int64_t* sensors, int32_t ns, const double* d_obs, double* J);
+
+/* Gradient dJ/d(ln k0) for the present linear Picard stage, whose solution
+ * the present state must be (coefficients and porosity as frozen for the
+ * stage).  The stage's residual Jacobian J_F is symmetric on this grid, so
+ * the adjoint J_F^T lambda = dJ/dx is solved by the stage's own PT sweep (FP64)
+ * with right-hand side dJ/dx, until its residual falls to rtol times
+ * max|dJ/dPf| (checked every nup sweeps) or max_iter; then
+ * dJ/d(ln k0_c) = -lambda^T dF/d(ln k0_c), from the Darcy flux of eq (20)
+ * (k = k0 (phi/phi0)^3), into grad_dev (FP64, field layout, cells).
+ * Synchronises.  PT_ENOTCONV if rtol is not met (gradient still written). */
+pt_status pt_adjoint_stage(pt_grid* g, const int64_t* sensors, int32_t ns, const double* d_obs, double rtol,
+                           int64_t max_iter, void* grad_dev, double* J, int64_t* iters, double* rho);
+
 /* Streaming copy of n doubles (achievable-bandwidth reference). */
 pt_status pt_copy(pt_grid* g, const void* src, void* dst, int64_t n);
 

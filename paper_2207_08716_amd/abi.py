@@ -46,7 +46,8 @@ EXPORTS = ["pt_create", "pt_destroy", "pt_field_elems", "pt_bind_field", "pt_wor
            "pt_refresh", "pt_iteration", "pt_iterate", "pt_last_norms", "pt_solve_linear",
            "pt_residual_reference", "pt_set_residual_reference",
            "pt_porosity_step", "pt_mixed_workspace_size", "pt_bind_mixed_workspace", "pt_residual",
-           "pt_solve_mixed", "pt_copy", "pt_status_str", "pt_last_error", "pt_abi_version"]
+           "pt_solve_mixed", "pt_adjoint_workspace_size", "pt_bind_adjoint_workspace", "pt_set_log_k0",
+           "pt_misfit", "pt_adjoint_stage", "pt_copy", "pt_status_str", "pt_last_error", "pt_abi_version"]
 
 _lib = None
 
@@ -92,6 +93,12 @@ def load(path: str = LIB_PATH):
     lib.pt_residual.argtypes = [vp]
     lib.pt_solve_mixed.argtypes = [vp, C.c_double, C.c_double, C.c_int64, C.c_int32,
                                    P(C.c_int64), P(C.c_int32), P(C.c_double)]
+    lib.pt_adjoint_workspace_size.argtypes = [vp, C.c_int32, P(C.c_size_t)]
+    lib.pt_bind_adjoint_workspace.argtypes = [vp, vp, C.c_size_t, C.c_int32]
+    lib.pt_set_log_k0.argtypes = [vp, vp]
+    lib.pt_misfit.argtypes = [vp, P(C.c_int64), C.c_int32, P(C.c_double), P(C.c_double)]
+    lib.pt_adjoint_stage.argtypes = [vp, P(C.c_int64), C.c_int32, P(C.c_double), C.c_double, C.c_int64, vp,
+                                     P(C.c_double), P(C.c_int64), P(C.c_double)]
     lib.pt_status_str.argtypes = [C.c_int]
     lib.pt_status_str.restype = C.c_char_p
     lib.pt_last_error.argtypes = [vp]

@@ -1,0 +1,49 @@
+"""torch.autograd.Function over the stage adjoint.
+
+LogKMisfit.apply(logk0, problem) runs one linear Picard stage from the
+problem's initial state with k0 = exp(logk0) and returns the sensor misfit
+J = 1/2 sum_s (Pf_s - d_s)^2; backward returns dJ/d(logk0) from the
+hand-written adjoint (pt_adjoint_stage).  Every step runs in the HIP library.
+"""
+from __future__ import annotations
+
+import torch
+
+
+class StageProblem:
+    """A Grid plus the data of one linear-stage misfit problem."""
+
+    def __init__(self, grid, phi, sensors, d_obs, rtol=1e-12, max_iter=2_000_000):
+        self.grid = grid
+        self.phi = phi
+        self.sensors = sensors
+        self.d_obs = d_obs
+        self.rtol = rtol
+        self.max_iter = max_iter
+
+    def forward(self, logk0) -> float:
+        g = self.grid
+        g.reset_state(self.phi)
+        g.set_log_k0(logk0)
+        g.begin_step(False)
+        g.refresh(1.0, 1.0)
+        it, rho, ok = g.solve_linear(self.rtol, self.max_iter)
+        if not ok:
+            raise RuntimeError(f"stage solve did not reach rtol {self.rtol} (rho {rho:.3e})")
+        return g.misfit(self.sensors, self.d_obs)
+
+
+class LogKMisfit(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, logk0: torch.Tensor, problem: StageProblem):
+        J = problem.forward(logk0.detach())
+        ctx.problem = problem
+        return logk0.new_tensor(J)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        p = ctx.problem
+        _J, grad, _it, _rho, ok = p.grid.adjoint_stage(p.sensors, p.d_obs, p.rtol, p.max_iter)
+        if not ok:
+            raise RuntimeError("adjoint solve did not converge")
+        return grad_out * grad.clone(), None

@@ -3,7 +3,9 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <algorithm>
 #include <string>
+#include <vector>
 
 #include "pt_internal.h"
 
@@ -17,6 +19,9 @@ struct pt_grid {
     int cur[PT_NPING];
     void* ws = nullptr;
     size_t ws_bytes = 0;
+    double* aws = nullptr;     // FP64 workspace of the stage adjoint
+    size_t aws_bytes = 0;
+    int32_t aws_sensors = 0;   // sensor capacity of the adjoint workspace
     float* mws = nullptr;      // FP32 workspace of the mixed-precision solve
     size_t mws_bytes = 0;
     bool mws_clean = false;    // both correction copies zeroed once
@@ -622,6 +627,165 @@ pt_status pt_solve_mixed(pt_grid* g, double rtol, double eta_in, int64_t max_inn
     }
     if (inner_iters) *inner_iters = inner_total;
     if (outer_iters) *outer_iters = outer;
+    if (rho) *rho = r;
+    return (r <= rtol) ? PT_OK : PT_ENOTCONV;
+}
+
+// ---- adjoint of a linear Picard stage ---------------------------------------
+namespace {
+// FP64 boxes: [0..7] lambda copy 0 (V, Pt, Pf, damped residual), [8..15] copy 1,
+// [16..20] right-hand side (f, r_Pt, r_Pf), [21] chi; then the sensor tail:
+// offsets (int64), gathered values, seeds.
+constexpr int AD_NBOX = 22;
+size_t ad_needed(const pt_grid* g, int32_t max_sensors) {
+    return (size_t)(AD_NBOX * mx_box(g) + 3 * (int64_t)max_sensors) * sizeof(double);
+}
+double* ad(pt_grid* g, int b) { return g->aws + (int64_t)b * mx_box(g); }
+int64_t* ad_offs(pt_grid* g) { return reinterpret_cast<int64_t*>(g->aws + AD_NBOX * mx_box(g)); }
+double* ad_vals(pt_grid* g) { return g->aws + AD_NBOX * mx_box(g) + g->aws_sensors; }
+double* ad_seed(pt_grid* g) { return g->aws + AD_NBOX * mx_box(g) + 2 * (int64_t)g->aws_sensors; }
+
+// Sensor cells (linear indices over the nx*ny*nz cells, x fastest) to
+// padded-box offsets, with range and distinctness checks.
+pt_status sensor_offsets(pt_grid* g, const int64_t* sensors, int32_t ns, std::vector<int64_t>& offs) {
+    const int64_t nc = (int64_t)g->geom.nx * g->geom.ny * g->geom.nz;
+    offs.resize(ns);
+    std::vector<int64_t> sorted(sensors, sensors + ns);
+    std::sort(sorted.begin(), sorted.end());
+    for (int32_t s = 0; s < ns; ++s) {
+        if (sorted[s] < 0 || sorted[s] >= nc) return fail(g, PT_EINVAL, "sensor cell out of range");
+        if (s > 0 && sorted[s] == sorted[s - 1]) return fail(g, PT_EINVAL, "duplicate sensor cell");
+        const int64_t c = sensors[s];
+        const int64_t i = c % g->geom.nx, j = (c / g->geom.nx) % g->geom.ny, k = c / ((int64_t)g->geom.nx * g->geom.ny);
+        offs[s] = k * g->geom.S + j * g->geom.P + i;
+    }
+    return PT_OK;
+}
+
+// J = 1/2 sum (Pf_s - d_s)^2 of the present state; leaves the gathered Pf in vals.
+pt_status misfit_impl(pt_grid* g, const int64_t* sensors, int32_t ns, const double* d_obs, double* J,
+                      std::vector<double>& resid) {
+    std::vector<int64_t> offs;
+    pt_status st = sensor_offsets(g, sensors, ns, offs);
+    if (st != PT_OK) return st;
+    hipError_t e = hipMemcpyAsync(ad_offs(g), offs.data(), ns * sizeof(int64_t), hipMemcpyHostToDevice, g->stream);
+    if (e != hipSuccess) return hip_fail(g, e, "sensor upload");
+    e = launch_gather(cur(g, PT_PF), ad_offs(g), ns, ad_vals(g), g->stream);
+    if (e != hipSuccess) return hip_fail(g, e, "gather");
+    std::vector<double> vals(ns);
+    e = hipMemcpyAsync(vals.data(), ad_vals(g), ns * sizeof(double), hipMemcpyDeviceToHost, g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) return hip_fail(g, e, "gather download");
+    resid.resize(ns);
+    double acc = 0.0;
+    for (int32_t s = 0; s < ns; ++s) {
+        resid[s] = vals[s] - d_obs[s];
+        acc += resid[s] * resid[s];
+    }
+    *J = 0.5 * acc;
+    return PT_OK;
+}
+}  // namespace
+
+pt_status pt_adjoint_workspace_size(const pt_grid* g, int32_t max_sensors, size_t* bytes) {
+    if (!g || !bytes || max_sensors < 1) return PT_EINVAL;
+    *bytes = ad_needed(g, max_sensors);
+    return PT_OK;
+}
+
+pt_status pt_bind_adjoint_workspace(pt_grid* g, void* dev_ptr, size_t bytes, int32_t max_sensors) {
+    if (!g) return PT_EINVAL;
+    if (max_sensors < 1 || !dev_ptr || (reinterpret_cast<uintptr_t>(dev_ptr) & 255u) ||
+        bytes < ad_needed(g, max_sensors))
+        return fail(g, PT_EINVAL, "adjoint workspace missing, unaligned or too small");
+    g->aws = static_cast<double*>(dev_ptr);
+    g->aws_bytes = bytes;
+    g->aws_sensors = max_sensors;
+    return PT_OK;
+}
+
+pt_status pt_set_log_k0(pt_grid* g, const void* logk0_dev) {
+    if (!g || !logk0_dev) return PT_EINVAL;
+    if (!(g->prm.flags & PT_F_K0FIELD) || !g->f[PT_K0][0]) return fail(g, PT_EINVAL, "no k0 field bound");
+    hipError_t e = launch_exp_cells(g->geom, static_cast<const double*>(logk0_dev), g->f[PT_K0][0], g->stream);
+    if (e != hipSuccess) return hip_fail(g, e, "exp");
+    return PT_OK;
+}
+
+pt_status pt_misfit(pt_grid* g, const int64_t* sensors, int32_t ns, const double* d_obs, double* J) {
+    if (!g || !sensors || !d_obs || !J) return PT_EINVAL;
+    if (!g->aws) return fail(g, PT_EINVAL, "adjoint workspace not bound");
+    if (ns < 1 || ns > g->aws_sensors) return fail(g, PT_EINVAL, "sensor count outside the workspace capacity");
+    std::vector<double> resid;
+    return misfit_impl(g, sensors, ns, d_obs, J, resid);
+}
+
+pt_status pt_adjoint_stage(pt_grid* g, const int64_t* sensors, int32_t ns, const double* d_obs, double rtol,
+                           int64_t max_iter, void* grad_dev, double* J, int64_t* iters, double* rho) {
+    if (!g || !sensors || !d_obs || !grad_dev || !(rtol > 0.0) || max_iter < 1) return PT_EINVAL;
+    pt_status st = check_ready(g);
+    if (st != PT_OK) return st;
+    if (!g->aws) return fail(g, PT_EINVAL, "adjoint workspace not bound");
+    if (ns < 1 || ns > g->aws_sensors) return fail(g, PT_EINVAL, "sensor count outside the workspace capacity");
+    if (reinterpret_cast<uintptr_t>(grad_dev) & 255u) return fail(g, PT_EINVAL, "gradient buffer unaligned");
+    double Jv = 0.0;
+    std::vector<double> resid;
+    st = misfit_impl(g, sensors, ns, d_obs, &Jv, resid);
+    if (st != PT_OK) return st;
+    double gmax = 0.0;
+    std::vector<double> seed(ns);
+    for (int32_t s = 0; s < ns; ++s) {
+        seed[s] = -resid[s];           // right-hand side: F_lin(lambda) = J lambda - dJ/dx
+        gmax = std::fmax(gmax, std::fabs(resid[s]));
+    }
+    const int64_t box_bytes = mx_box(g) * (int64_t)sizeof(double);
+    hipError_t e = hipMemsetAsync(ad(g, 0), 0, 21 * box_bytes, g->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(ad_seed(g), seed.data(), ns * sizeof(double), hipMemcpyHostToDevice, g->stream);
+    if (e == hipSuccess) e = launch_scatter(ad_seed(g), ad_offs(g), ns, ad(g, 20), g->stream);
+    if (e == hipSuccess) e = launch_chi64(g->geom, cur(g, PT_ETA), cur(g, PT_LP), ad(g, 21), g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) return hip_fail(g, e, "adjoint set-up");
+    int cp = 0;
+    int64_t it = 0;
+    double r = 0.0;
+    if (gmax > 0.0) {
+        const int64_t nup = g->prm.nup;
+        r = INFINITY;
+        while (it < max_iter) {
+            ++it;
+            const bool chk = (it % nup == 0);
+            SweepPtrs<double> p{};
+            const int src = cp ? 8 : 0, dst = cp ? 0 : 8;
+            p.vx = ad(g, src + 0); p.vy = ad(g, src + 1); p.vz = ad(g, src + 2);
+            p.pt = ad(g, src + 3); p.pf = ad(g, src + 4);
+            p.rx = ad(g, src + 5); p.ry = ad(g, src + 6); p.rz = ad(g, src + 7);
+            p.vx_o = ad(g, dst + 0); p.vy_o = ad(g, dst + 1); p.vz_o = ad(g, dst + 2);
+            p.pt_o = ad(g, dst + 3); p.pf_o = ad(g, dst + 4);
+            p.rx_o = ad(g, dst + 5); p.ry_o = ad(g, dst + 6); p.rz_o = ad(g, dst + 7);
+            p.fox = ad(g, 16); p.foy = ad(g, 17); p.foz = ad(g, 18);
+            p.pto = ad(g, 19); p.pfo = ad(g, 20);
+            p.eta = ad(g, 21); p.kc = cur(g, PT_KC); p.mus = cur(g, PT_MUS);
+            p.partials = static_cast<double*>(g->ws);
+            e = launch_correction64(g->geom, g->coef, p, chk ? 1 : 0, g->stream);
+            if (e != hipSuccess) return hip_fail(g, e, "adjoint sweep");
+            cp ^= 1;
+            if (chk) {
+                st = reduce_norms(g);
+                if (st != PT_OK) return st;
+                pt_norms nm;
+                st = read_norms(g, &nm);
+                if (st != PT_OK) return st;
+                r = group_rho(nm, gmax, gmax);
+                if (r <= rtol) break;
+            }
+        }
+    }
+    e = launch_adjoint_gradient(g->geom, g->coef, cur(g, PT_KC), cur(g, PT_PF), ad(g, (cp ? 8 : 0) + 4),
+                                static_cast<double*>(grad_dev), g->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) return hip_fail(g, e, "adjoint gradient");
+    if (J) *J = Jv;
+    if (iters) *iters = it;
     if (rho) *rho = r;
     return (r <= rtol) ? PT_OK : PT_ENOTCONV;
 }

@@ -327,6 +327,64 @@ __global__ __launch_bounds__(AB) void k_apply_correction(Geom g, MixedPtrs m) {
     }
 }
 
+// ---- adjoint of a linear Picard stage -------------------------------------
+__global__ void k_gather(const double* __restrict__ src, const int64_t* __restrict__ offs, int n,
+                         double* __restrict__ out) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) out[t] = src[offs[t]];
+}
+
+__global__ void k_scatter(const double* __restrict__ vals, const int64_t* __restrict__ offs, int n,
+                          double* __restrict__ dst) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) dst[offs[t]] = vals[t];
+}
+
+// chi = 1/((1-phi) eta_phi) with the porosity frozen for the stage.
+__global__ __launch_bounds__(AB) void k_chi64(Geom g, const double* __restrict__ eta,
+                                              const double* __restrict__ lp, double* __restrict__ chi) {
+    Idx q;
+    if (!box_index(g, (int64_t)blockIdx.x * AB + threadIdx.x, q)) return;
+    if (q.i >= g.nx || q.j >= g.ny || q.k >= g.nz) return;
+    const int64_t o = at(g, q.i, q.j, q.k);
+    chi[o] = 1.0 / (eta[o] * exp(lp[o]));
+}
+
+// dJ/d(ln k0) at cell c = -K_c * sum over c's interior faces of
+// -(1/2) ((Pf_H - Pf_L)/h + b) (lam_L - lam_H)/h, from the Darcy flux
+// q = -(K_L + K_H)/2 ((Pf_H - Pf_L)/h + b) that r_Pf carries as +q/h in the
+// lower cell L and -q/h in the upper cell H (b: buoyancy term, z only).
+__global__ __launch_bounds__(AB) void k_adjoint_gradient(Geom g, Coef c, const double* __restrict__ kc,
+                                                         const double* __restrict__ pf,
+                                                         const double* __restrict__ lam,
+                                                         double* __restrict__ grad) {
+    Idx q;
+    if (!box_index(g, (int64_t)blockIdx.x * AB + threadIdx.x, q)) return;
+    const int i = q.i, j = q.j, k = q.k;
+    if (i >= g.nx || j >= g.ny || k >= g.nz) return;
+    const int64_t o = at(g, i, j, k);
+    double acc = 0.0;
+    auto face = [&](int64_t lo, int64_t hi, double hinv, double b) {
+        const double gf = (pf[hi] - pf[lo]) * hinv + b;
+        acc += -0.5 * gf * (lam[lo] - lam[hi]) * hinv;
+    };
+    if (i > 0) face(at(g, i - 1, j, k), o, c.dxi, 0.0);
+    if (i < g.nx - 1) face(o, at(g, i + 1, j, k), c.dxi, 0.0);
+    if (j > 0) face(at(g, i, j - 1, k), o, c.dyi, 0.0);
+    if (j < g.ny - 1) face(o, at(g, i, j + 1, k), c.dyi, 0.0);
+    if (k > 0) face(at(g, i, j, k - 1), o, c.dzi, c.buoy);
+    if (k < g.nz - 1) face(o, at(g, i, j, k + 1), c.dzi, c.buoy);
+    grad[o] = -kc[o] * acc;
+}
+
+__global__ __launch_bounds__(AB) void k_exp_cells(Geom g, const double* __restrict__ src, double* __restrict__ dst) {
+    Idx q;
+    if (!box_index(g, (int64_t)blockIdx.x * AB + threadIdx.x, q)) return;
+    if (q.i >= g.nx || q.j >= g.ny || q.k >= g.nz) return;
+    const int64_t o = at(g, q.i, q.j, q.k);
+    dst[o] = exp(src[o]);
+}
+
 inline dim3 box_grid(const Geom& g) {
     const int64_t n = (int64_t)(g.nx + 1) * (g.ny + 1) * (g.nz + 1);
     return dim3((unsigned)((n + AB - 1) / AB));
@@ -365,6 +423,32 @@ hipError_t launch_prepare_mixed(const Geom& g, const MixedPtrs& m, hipStream_t s
 
 hipError_t launch_apply_correction(const Geom& g, const MixedPtrs& m, hipStream_t s) {
     hipLaunchKernelGGL(k_apply_correction, box_grid(g), dim3(AB), 0, s, g, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const double* src, const int64_t* offs, int n, double* out, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_gather, dim3((n + 255) / 256), dim3(256), 0, s, src, offs, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(const double* vals, const int64_t* offs, int n, double* dst, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(k_scatter, dim3((n + 255) / 256), dim3(256), 0, s, vals, offs, n, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_chi64(const Geom& g, const double* eta, const double* lp, double* chi, hipStream_t s) {
+    hipLaunchKernelGGL(k_chi64, box_grid(g), dim3(AB), 0, s, g, eta, lp, chi);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_gradient(const Geom& g, const Coef& c, const double* kc, const double* pf,
+                                   const double* lam_pf, double* grad, hipStream_t s) {
+    hipLaunchKernelGGL(k_adjoint_gradient, box_grid(g), dim3(AB), 0, s, g, c, kc, pf, lam_pf, grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_exp_cells(const Geom& g, const double* src, double* dst, hipStream_t s) {
+    hipLaunchKernelGGL(k_exp_cells, box_grid(g), dim3(AB), 0, s, g, src, dst);
     return hipGetLastError();
 }
 

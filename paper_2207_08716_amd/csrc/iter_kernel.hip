@@ -509,6 +509,15 @@ hipError_t launch_correction(const Geom& g, const Coef& c, const SweepPtrs<float
     return hipGetLastError();
 }
 
+hipError_t launch_correction64(const Geom& g, const Coef& c, const SweepPtrs<double>& p, int norms,
+                               hipStream_t s) {
+    const dim3 block(BX, BY, 1);
+    const dim3 grid((unsigned)iter_grid_blocks(g), 1, 1);
+    if (norms) hipLaunchKernelGGL((k_sweep<double, MD_CORR, true>), grid, block, 0, s, g, c, p);
+    else hipLaunchKernelGGL((k_sweep<double, MD_CORR, false>), grid, block, 0, s, g, c, p);
+    return hipGetLastError();
+}
+
 hipError_t launch_reduce_max(const double* partials, int64_t nblocks, double* out8, hipStream_t s) {
     hipLaunchKernelGGL(k_reduce_max, dim3(1), dim3(256), 0, s, partials, nblocks, out8);
     return hipGetLastError();

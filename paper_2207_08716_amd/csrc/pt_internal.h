@@ -84,6 +84,8 @@ hipError_t launch_iteration(const Geom& g, const Coef& c, const SweepPtrs<double
                             int norms, hipStream_t s);
 hipError_t launch_correction(const Geom& g, const Coef& c, const SweepPtrs<float>& p, int norms,
                              hipStream_t s);
+hipError_t launch_correction64(const Geom& g, const Coef& c, const SweepPtrs<double>& p, int norms,
+                               hipStream_t s);
 hipError_t launch_reduce_max(const double* partials, int64_t nblocks, double* out8, hipStream_t s);
 
 struct AuxPtrs {
@@ -124,6 +126,14 @@ struct MixedPtrs {
     float *kc32, *mus32, *chi32;
 };
 hipError_t launch_prepare_mixed(const Geom& g, const MixedPtrs& m, hipStream_t s);
+
+// Adjoint of a linear Picard stage.
+hipError_t launch_gather(const double* src, const int64_t* offs, int n, double* out, hipStream_t s);
+hipError_t launch_scatter(const double* vals, const int64_t* offs, int n, double* dst, hipStream_t s);
+hipError_t launch_chi64(const Geom& g, const double* eta, const double* lp, double* chi, hipStream_t s);
+hipError_t launch_adjoint_gradient(const Geom& g, const Coef& c, const double* kc, const double* pf,
+                                   const double* lam_pf, double* grad, hipStream_t s);
+hipError_t launch_exp_cells(const Geom& g, const double* src, double* dst, hipStream_t s);
 hipError_t launch_apply_correction(const Geom& g, const MixedPtrs& m, hipStream_t s);
 
 }  // namespace ptk

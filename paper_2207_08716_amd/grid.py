@@ -221,6 +221,71 @@ class Grid:
                                                                C.byref(rho)), "solve_mixed")
         return inner.value, outer.value, rho.value, st == 0
 
+    # ---- stage adjoint ------------------------------------------------------
+    def enable_adjoint(self, max_sensors=64):
+        """Allocate and bind the FP64 workspace of the stage adjoint."""
+        if getattr(self, "aws", None) is not None and self.aws_sensors >= max_sensors:
+            return
+        nbytes = C.c_size_t()
+        _check(self.lib, self.h, self.lib.pt_adjoint_workspace_size(self.h, int(max_sensors), C.byref(nbytes)),
+               "adjoint size")
+        with torch.cuda.stream(self.stream):
+            self.aws = torch.zeros((nbytes.value + 7) // 8, dtype=torch.float64, device=self.device)
+            self.grad_buf = torch.zeros(self.buf["pt"][0].shape, dtype=torch.float64, device=self.device)
+        _check(self.lib, self.h, self.lib.pt_bind_adjoint_workspace(self.h, C.c_void_p(self.aws.data_ptr()),
+                                                                    nbytes.value, int(max_sensors)), "bind adjoint")
+        self.aws_sensors = max_sensors
+
+    def set_log_k0(self, logk0):
+        """k0 <- exp(logk0): logk0 a (nz, ny, nx) array or device tensor."""
+        if not self.k0field:
+            raise ValueError("grid created without a k0 field")
+        with torch.cuda.stream(self.stream):
+            box = torch.zeros(self.buf["pt"][0].shape, dtype=torch.float64, device=self.device)
+            t = torch.as_tensor(logk0, dtype=torch.float64, device=self.device)
+            box[:self.nz, :self.ny, :self.nx].copy_(t)
+        _check(self.lib, self.h, self.lib.pt_set_log_k0(self.h, C.c_void_p(box.data_ptr())), "set_log_k0")
+        self.stream.synchronize()
+
+    def misfit(self, sensors, d_obs) -> float:
+        self.enable_adjoint(max(64, len(sensors)))
+        s_arr = np.ascontiguousarray(sensors, dtype=np.int64)
+        d_arr = np.ascontiguousarray(d_obs, dtype=np.float64)
+        J = C.c_double()
+        _check(self.lib, self.h, self.lib.pt_misfit(self.h, s_arr.ctypes.data_as(C.POINTER(C.c_int64)), len(s_arr),
+                                                    d_arr.ctypes.data_as(C.POINTER(C.c_double)), C.byref(J)), "misfit")
+        return J.value
+
+    def adjoint_stage(self, sensors, d_obs, rtol=1e-12, max_iter=2_000_000):
+        """J and dJ/d(ln k0) (device tensor view, cells) for the present
+        linear Picard stage (see pt_adjoint_stage)."""
+        self.enable_adjoint(max(64, len(sensors)))
+        s_arr = np.ascontiguousarray(sensors, dtype=np.int64)
+        d_arr = np.ascontiguousarray(d_obs, dtype=np.float64)
+        J = C.c_double()
+        it = C.c_int64()
+        rho = C.c_double()
+        st = _check(self.lib, self.h, self.lib.pt_adjoint_stage(
+            self.h, s_arr.ctypes.data_as(C.POINTER(C.c_int64)), len(s_arr),
+            d_arr.ctypes.data_as(C.POINTER(C.c_double)), float(rtol), int(max_iter),
+            C.c_void_p(self.grad_buf.data_ptr()), C.byref(J), C.byref(it), C.byref(rho)), "adjoint_stage")
+        return J.value, self.grad_buf[:self.nz, :self.ny, :self.nx], it.value, rho.value, st == 0
+
+    def reset_state(self, phi):
+        """Back to the initial state of every workload (V = R = 0, pressures
+        and stress history 0, ln(1-phi) from phi, Mn = mu0), keeping k0."""
+        for name in ("vx", "vy", "vz", "pt", "pf", "rx", "ry", "rz", "pto", "pfo",
+                     "sxx", "syy", "szz", "sxy", "sxz", "syz", "fox", "foy", "foz"):
+            self.set(name, 0.0)
+        ph = self.phys
+        lp = np.log(1.0 - np.asarray(phi, dtype=np.float64))
+        self.set("lp", lp)
+        self.set("lpo", lp)
+        self.set("mn", ph.mu0)
+        self.set("eta", 1.0)
+        self.set("mus", ph.mu0 * ph.phi0 * ph.cmu)
+        self.set("kc", ph.kmuf0)
+
     def copy(self, src: torch.Tensor, dst: torch.Tensor):
         assert src.dtype == dst.dtype == torch.float64 and src.numel() == dst.numel()
         _check(self.lib, self.h, self.lib.pt_copy(self.h, C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()),

@@ -238,7 +238,8 @@ def config_adjoint(n: int = 127, seed: int = 4) -> Config:
     field (correlation 0.1, sigma 0.5), 10 steps of 5 Picard stages."""
     c = config_parity(n, seed)
     return dataclasses.replace(c, name=f"adjoint{n}", k0_kind="grf", k0_seed=seed,
-                               mode="picard", n_picard=5, rtol=1e-10, n_steps=10)
+                               mode="picard", n_picard=5, rtol=1e-10, n_steps=10,
+                               phys=c.phys.replace(dt=PICARD_DT, dtS=PICARD_DT))
 
 
 def config_waves(n: int = 767, seed: int = 8) -> Config:

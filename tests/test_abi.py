@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared():
     text = open(os.path.join(ROOT, "include", "ptporo.h")).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(pt_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(pt_[a-z_0-9]+)\s*\(", text)))
 
 
 @pytest.fixture(scope="module")
