@@ -59,7 +59,8 @@ class _Params(C.Structure):
                 ("rho_i", C.c_double), ("c_v", C.c_double), ("c_pf", C.c_double),
                 ("damp_c", C.c_double),
                 ("powerlaw", C.c_int32), ("dpcap", C.c_int32), ("mech_off", C.c_int32),
-                ("k0field", C.c_int32)]
+                ("k0field", C.c_int32), ("ngx", C.c_int32), ("ngy", C.c_int32), ("ngz", C.c_int32),
+                ("hx", C.c_double), ("hy", C.c_double), ("hz", C.c_double)]
 
 
 _STATE_FIELDS = ("vx", "vy", "vz", "pt", "pf", "lp", "rx", "ry", "rz", "pto", "pfo",
@@ -127,14 +128,22 @@ class Oracle:
     phi:  initial porosity, (nz, ny, nx).  k0: per-cell k0/mu_f or None.
     """
 
-    def __init__(self, phys, nx, ny, nz, phi, k0=None):
+    def __init__(self, phys, nx, ny, nz, phi, k0=None, global_counts=None):
+        """global_counts: (nx, ny, nz) of the full grid on the domain of phys
+        when these arrays are a window of it (the spacing, the damping and
+        the Pt pseudo-step are the full grid's)."""
         self.phys = phys
         self.nx, self.ny, self.nz = nx, ny, nz
         self.lib = _load()
         p = _Params()
         p.nx, p.ny, p.nz = nx, ny, nz
-        for name, _ in _Params._fields_[3:-4]:
+        for name, _ in _Params._fields_[3:-10]:
             setattr(p, name, float(getattr(phys, name)))
+        if global_counts is not None:
+            # a window of a (gx, gy, gz) grid on the full domain of phys
+            gx, gy, gz = (int(v) for v in global_counts)
+            p.ngx, p.ngy, p.ngz = gx, gy, gz
+            p.hx, p.hy, p.hz = phys.lx / gx, phys.ly / gy, phys.lz / gz
         p.powerlaw = int(bool(phys.powerlaw))
         p.dpcap = int(bool(phys.dpcap))
         p.mech_off = int(bool(phys.mech_off))

@@ -42,6 +42,12 @@ typedef struct {
     double dt, dtS;
     double beta_n, rho_i, c_v, c_pf, damp_c;
     int32_t powerlaw, dpcap, mech_off, k0field;
+    /* Grid counts used by the damping (1 - damp_c/n) and the Pt pseudo-step
+     * (n_max) when the arrays cover only a window of a larger grid; 0 means
+     * the arrays' own counts. */
+    int32_t ngx, ngy, ngz;
+    /* Grid spacings of the full grid for such a window (0: l/n). */
+    double hx, hy, hz;
 } or_params;
 
 /* Solver state: every pointer is a dense FP64 array, x fastest.
@@ -98,10 +104,15 @@ or_ctx *or_create(const or_params *p)
     or_ctx *c = (or_ctx *)calloc(1, sizeof(or_ctx));
     c->p = *p;
     c->nx = p->nx; c->ny = p->ny; c->nz = p->nz;
-    c->dx = p->lx / p->nx; c->dy = p->ly / p->ny; c->dz = p->lz / p->nz;
+    c->dx = p->hx > 0.0 ? p->hx : p->lx / p->nx;
+    c->dy = p->hy > 0.0 ? p->hy : p->ly / p->ny;
+    c->dz = p->hz > 0.0 ? p->hz : p->lz / p->nz;
     c->h = dmin(c->dx, dmin(c->dy, c->dz));
-    c->nmax = p->nx > p->ny ? p->nx : p->ny;
-    if (p->nz > c->nmax) c->nmax = p->nz;
+    {
+        int gx = p->ngx > 0 ? p->ngx : p->nx, gy = p->ngy > 0 ? p->ngy : p->ny, gz = p->ngz > 0 ? p->ngz : p->nz;
+        c->nmax = gx > gy ? gx : gy;
+        if (gz > c->nmax) c->nmax = gz;
+    }
     size_t nx = p->nx, ny = p->ny, nz = p->nz;
     c->nc = nx * ny * nz;
     c->nfx = (nx + 1) * ny * nz; c->nfy = nx * (ny + 1) * nz; c->nfz = nx * ny * (nz + 1);
@@ -540,7 +551,9 @@ void or_iteration(or_ctx *c, or_state *st, int update_lp, double *norms)
     momentum(c, c->ptn);
 
     /* Damped velocity update: R' = f/rho_i + d R, V' = V + dtau_V R'. */
-    const double dmx = 1.0 - p->damp_c / nx, dmy = 1.0 - p->damp_c / ny, dmz = 1.0 - p->damp_c / nz;
+    const double dmx = 1.0 - p->damp_c / (p->ngx > 0 ? p->ngx : nx);
+    const double dmy = 1.0 - p->damp_c / (p->ngy > 0 ? p->ngy : ny);
+    const double dmz = 1.0 - p->damp_c / (p->ngz > 0 ? p->ngz : nz);
     memcpy(c->vxn, st->vx, c->nfx * sizeof(double));
     memcpy(c->vyn, st->vy, c->nfy * sizeof(double));
     memcpy(c->vzn, st->vz, c->nfz * sizeof(double));
