@@ -66,10 +66,11 @@ class _Params(C.Structure):
 _STATE_FIELDS = ("vx", "vy", "vz", "pt", "pf", "lp", "rx", "ry", "rz", "pto", "pfo",
                  "lpo", "sxx", "syy", "szz", "sxy", "sxz", "syz", "mn", "k0", "kc",
                  "eta", "mus")
+_SOURCE_FIELDS = ("fsx", "fsy", "fsz")
 
 
 class _State(C.Structure):
-    _fields_ = [(n, C.POINTER(C.c_double)) for n in _STATE_FIELDS]
+    _fields_ = [(n, C.POINTER(C.c_double)) for n in _STATE_FIELDS + _SOURCE_FIELDS]
 
 
 _lib = None
@@ -168,12 +169,30 @@ class Oracle:
         self.f["eta"][...] = 1.0
         self.f["mus"][...] = phys.mu0 * phys.phi0 * phys.cmu
         self.f["kc"][...] = phys.kmuf0
-        self._st = _State(*[_ptr(self.f[n]) for n in _STATE_FIELDS])
+        self.source = None     # optional momentum source (adjoint solves only)
+        self._bind()
         self.refreshed = False
         self.step_index = 0
         self.iter = 0          # iteration counter within the current step
         self.total_iters = 0
         self.history = []      # norms at each check
+
+    def _bind(self):
+        src = [None] * 3 if self.source is None else [_ptr(a) for a in self.source]
+        self._st = _State(*([_ptr(self.f[n]) for n in _STATE_FIELDS] + src))
+
+    def set_momentum_source(self, fx, fy, fz):
+        """Additive momentum source on the interior faces (None: remove).  Not
+        part of the method: the adjoint uses it to impose a right-hand side
+        on the momentum rows of a transposed solve."""
+        if fx is None:
+            self.source = None
+        else:
+            sh = field_shapes(self.nx, self.ny, self.nz)
+            self.source = tuple(np.ascontiguousarray(a, dtype=np.float64).copy()
+                                for a in (fx, fy, fz))
+            assert [a.shape for a in self.source] == [sh["vx"], sh["vy"], sh["vz"]]
+        self._bind()
 
     def __del__(self):
         try:

@@ -65,6 +65,10 @@ typedef struct {
     double *mn;                    /* lagged shear-viscosity factor (cells)  */
     double *k0;                    /* per-cell k0/mu_f, used if k0field      */
     double *kc, *eta, *mus;        /* lagged k/mu_f, eta_phi, mu_s (cells)   */
+    /* Optional additive momentum source on the faces (NULL: none).  Only the
+     * adjoint's transposed solves set it, to impose a right-hand side on the
+     * momentum rows; the method itself has no such term.                    */
+    double *fsx, *fsy, *fsz;
 } or_state;
 
 typedef struct {
@@ -358,9 +362,10 @@ static void stresses(or_ctx *c, const or_state *st, int with_betan)
 
 /* ---- stage 5: total momentum balance, eq (19) (interior faces) ------------- */
 /* f = div(tau) - grad P - (rho g - rho_bg g) e_z, with P the pressure given
- * (the updated Pt in the PT iteration, the current Pt for the residual).
+ * (the updated Pt in the PT iteration, the current Pt for the residual),
+ * plus the optional source of the state.
  * Boundary faces: f = 0 (not updated, normal velocity fixed at zero).        */
-static void momentum(or_ctx *c, const double *ptp)
+static void momentum(or_ctx *c, const or_state *st, const double *ptp)
 {
     const double rbg = rhobg_g(c);
 #pragma omp parallel for
@@ -373,6 +378,7 @@ static void momentum(or_ctx *c, const double *ptp)
                       + (c->txy[IEXY(i, j + 1, k)] - c->txy[IEXY(i, j, k)]) / c->dy
                       + (c->txz[IEXZ(i, j, k + 1)] - c->txz[IEXZ(i, j, k)]) / c->dz
                       - (ptp[IC(i, j, k)] - ptp[IC(i - 1, j, k)]) / c->dx;
+                if (st->fsx && i > 0 && i < NX) f += st->fsx[IFX(i, j, k)];
                 c->fx[IFX(i, j, k)] = f;
             }
 #pragma omp parallel for
@@ -385,6 +391,7 @@ static void momentum(or_ctx *c, const double *ptp)
                       + (c->tyy[IC(i, j, k)] - c->tyy[IC(i, j - 1, k)]) / c->dy
                       + (c->tyz[IEYZ(i, j, k + 1)] - c->tyz[IEYZ(i, j, k)]) / c->dz
                       - (ptp[IC(i, j, k)] - ptp[IC(i, j - 1, k)]) / c->dy;
+                if (st->fsy && j > 0 && j < NY) f += st->fsy[IFY(i, j, k)];
                 c->fy[IFY(i, j, k)] = f;
             }
 #pragma omp parallel for
@@ -398,6 +405,7 @@ static void momentum(or_ctx *c, const double *ptp)
                       + (c->tzz[IC(i, j, k)] - c->tzz[IC(i, j, k - 1)]) / c->dz
                       - (ptp[IC(i, j, k)] - ptp[IC(i, j, k - 1)]) / c->dz
                       - (0.5 * (c->rhog[IC(i, j, k - 1)] + c->rhog[IC(i, j, k)]) - rbg);
+                if (st->fsz && k > 0 && k < NZ) f += st->fsz[IFZ(i, j, k)];
                 c->fz[IFZ(i, j, k)] = f;
             }
 }
@@ -488,7 +496,7 @@ void or_residual(or_ctx *c, const or_state *st, double *fx, double *fy, double *
     total_pressure_residual(c, st, st->pt);
     fluid_pressure_residual(c, st);
     stresses(c, st, 0);
-    momentum(c, st->pt);
+    momentum(c, st, st->pt);
     if (fx) memcpy(fx, c->fx, c->nfx * sizeof(double));
     if (fy) memcpy(fy, c->fy, c->nfy * sizeof(double));
     if (fz) memcpy(fz, c->fz, c->nfz * sizeof(double));
@@ -548,7 +556,7 @@ void or_iteration(or_ctx *c, or_state *st, int update_lp, double *norms)
      * momentum with the updated Pt'. */
     total_pressure_residual(c, st, c->ptn);
     stresses(c, st, 1);
-    momentum(c, c->ptn);
+    momentum(c, st, c->ptn);
 
     /* Damped velocity update: R' = f/rho_i + d R, V' = V + dtau_V R'. */
     const double dmx = 1.0 - p->damp_c / (p->ngx > 0 ? p->ngx : nx);
