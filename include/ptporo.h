@@ -254,6 +254,35 @@ pt_status pt_misfit(pt_grid* g, const int64_t* sensors, int32_t ns, const double
 pt_status pt_adjoint_stage(pt_grid* g, const int64_t* sensors, int32_t ns, const double* d_obs, double rtol,
                            int64_t max_iter, void* grad_dev, double* J, int64_t* iters, double* rho);
 
+/* ---- Adjoint of a recorded Picard run ------------------------------------
+ * The run: from the present state, n_steps physical steps (the first without
+ * a stress-history update, the later ones with it, eq (21)), each of
+ * n_picard stages: refresh without relaxation (eqs (23)-(26)), linear solve
+ * to rtol (as pt_solve_linear, reference of the step), porosity step
+ * (eq (22)).  J = 1/2 sum_s (Pf_s - d_s)^2 at the end of the run.
+ * The gradient dJ/d(ln k0) is the discrete adjoint of the converged run:
+ * per stage in reverse order, the adjoint of the porosity step, the
+ * transposed stage solve (the stage Jacobian is symmetric: FP64 PT sweeps
+ * to adj_rtol times the right-hand side's max norm), the adjoints of k/mu_f,
+ * 1/((1-phi) eta_phi), the buoyancy and the old values, and the chain of the
+ * refresh k = k0 (phi/phi0)^3, eta_phi ~ phi0/phi back to the stage's
+ * incoming ln(1-phi); per step boundary, the old values and the stress
+ * history (So = a So_prev + b E(V), with history term div(a So)) carry the
+ * adjoint to the previous step.  The decompaction switch R is piecewise
+ * constant (no derivative).  Needs PT_F_K0FIELD and the Newtonian law (no
+ * PT_F_POWERLAW, PT_F_DPCAP, PT_F_MECHOFF), and the adjoint workspace.
+ *
+ * The tape (caller-owned device buffer, 256-byte aligned, at least
+ * pt_adjoint_tape_size bytes) receives every stage's V, Pt, Pf, incoming
+ * ln(1-phi), k/mu_f and eta_phi: 8 padded boxes per stage.  grad_dev: one
+ * FP64 padded box, overwritten (cells).  On return the grid holds the end
+ * state of the run.  Synchronises.  PT_ENOTCONV if a forward or transposed
+ * solve misses its tolerance within max_iter (nothing after it is computed). */
+pt_status pt_adjoint_tape_size(const pt_grid* g, int32_t n_steps, int32_t n_picard, size_t* bytes);
+pt_status pt_adjoint_run(pt_grid* g, int32_t n_steps, int32_t n_picard, double rtol, double adj_rtol,
+                         int64_t max_iter, const int64_t* sensors, int32_t ns, const double* d_obs, void* tape,
+                         size_t tape_bytes, void* grad_dev, double* J, int64_t* fwd_iters, int64_t* adj_iters);
+
 /* Streaming copy of n doubles (achievable-bandwidth reference). */
 pt_status pt_copy(pt_grid* g, const void* src, void* dst, int64_t n);
 

@@ -47,7 +47,7 @@ EXPORTS = ["pt_create", "pt_destroy", "pt_field_elems", "pt_bind_field", "pt_wor
            "pt_residual_reference", "pt_set_residual_reference",
            "pt_porosity_step", "pt_mixed_workspace_size", "pt_bind_mixed_workspace", "pt_residual",
            "pt_solve_mixed", "pt_adjoint_workspace_size", "pt_bind_adjoint_workspace", "pt_set_log_k0",
-           "pt_misfit", "pt_adjoint_stage", "pt_copy", "pt_status_str", "pt_last_error", "pt_abi_version"]
+           "pt_misfit", "pt_adjoint_stage", "pt_adjoint_tape_size", "pt_adjoint_run", "pt_copy", "pt_status_str", "pt_last_error", "pt_abi_version"]
 
 _lib = None
 
@@ -99,6 +99,10 @@ def load(path: str = LIB_PATH):
     lib.pt_misfit.argtypes = [vp, P(C.c_int64), C.c_int32, P(C.c_double), P(C.c_double)]
     lib.pt_adjoint_stage.argtypes = [vp, P(C.c_int64), C.c_int32, P(C.c_double), C.c_double, C.c_int64, vp,
                                      P(C.c_double), P(C.c_int64), P(C.c_double)]
+    lib.pt_adjoint_tape_size.argtypes = [vp, C.c_int32, C.c_int32, P(C.c_size_t)]
+    lib.pt_adjoint_run.argtypes = [vp, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_int64,
+                                   P(C.c_int64), C.c_int32, P(C.c_double), vp, C.c_size_t, vp,
+                                   P(C.c_double), P(C.c_int64), P(C.c_int64)]
     lib.pt_status_str.argtypes = [C.c_int]
     lib.pt_status_str.restype = C.c_char_p
     lib.pt_last_error.argtypes = [vp]

@@ -634,9 +634,15 @@ pt_status pt_solve_mixed(pt_grid* g, double rtol, double eta_in, int64_t max_inn
 // ---- adjoint of a linear Picard stage ---------------------------------------
 namespace {
 // FP64 boxes: [0..7] lambda copy 0 (V, Pt, Pf, damped residual), [8..15] copy 1,
-// [16..20] right-hand side (f, r_Pt, r_Pf), [21] chi; then the sensor tail:
-// offsets (int64), gathered values, seeds.
-constexpr int AD_NBOX = 22;
+// [16..20] right-hand side (f, r_Pt, r_Pf), [21] chi; for the run adjoint
+// [22], [23] L_bar in/out, [24] eta_bar, [25] s_bar, [26..28] Pto/Pfo/Lo
+// adjoints, [29..31] history-term adjoint, [32..37] So adjoint (xx yy zz xy xz
+// yz); then the sensor tail: offsets (int64), gathered values, seeds.
+constexpr int AD_NBOX = 38;
+constexpr int AD_RHS = 16, AD_CHI = 21, AD_LBAR = 22, AD_ETAB = 24, AD_SB = 25, AD_OLD = 26, AD_FB = 29,
+              AD_SO = 32;
+// per recorded stage: V (3), Pt, Pf, incoming ln(1-phi), k/mu_f, eta_phi
+constexpr int TAPE_NBOX = 8;
 size_t ad_needed(const pt_grid* g, int32_t max_sensors) {
     return (size_t)(AD_NBOX * mx_box(g) + 3 * (int64_t)max_sensors) * sizeof(double);
 }
@@ -685,6 +691,66 @@ pt_status misfit_impl(pt_grid* g, const int64_t* sensors, int32_t ns, const doub
     *J = 0.5 * acc;
     return PT_OK;
 }
+// Transposed stage solve J_F lambda = xbar with -xbar in boxes AD_RHS..+4,
+// the coefficients k/mu_f = kc, mu_s = mus and chi in box AD_CHI, by the FP64
+// correction sweep (J_F is symmetric).  lambda starts at zero; convergence
+// when both residual groups fall to rtol times max|xbar|.  Returns the copy
+// (0 or 1) holding lambda.
+pt_status transposed_solve(pt_grid* g, const double* kc, const double* mus, double rtol, int64_t max_iter,
+                           int* lam_copy, int64_t* iters, double* rho) {
+    const int64_t box_bytes = mx_box(g) * (int64_t)sizeof(double);
+    hipError_t e = hipMemsetAsync(ad(g, 0), 0, 16 * box_bytes, g->stream);
+    if (e != hipSuccess) return hip_fail(g, e, "adjoint clear");
+    const int64_t nb = iter_grid_blocks(g->geom);
+    const double* rhs[5] = {ad(g, AD_RHS), ad(g, AD_RHS + 1), ad(g, AD_RHS + 2), ad(g, AD_RHS + 3), ad(g, AD_RHS + 4)};
+    e = launch_absmax5(g->geom, rhs, static_cast<double*>(g->ws), nb, g->stream);
+    if (e != hipSuccess) return hip_fail(g, e, "rhs norm");
+    pt_status st = reduce_norms(g);
+    if (st != PT_OK) return st;
+    pt_norms n0;
+    st = read_norms(g, &n0);
+    if (st != PT_OK) return st;
+    const double ref = n0.f;
+    int cp = 0;
+    int64_t it = 0;
+    double r = 0.0;
+    if (ref > 0.0) {
+        const int64_t nup = g->prm.nup;
+        r = INFINITY;
+        while (it < max_iter) {
+            ++it;
+            const bool chk = (it % nup == 0);
+            SweepPtrs<double> p{};
+            const int src = cp ? 8 : 0, dst = cp ? 0 : 8;
+            p.vx = ad(g, src + 0); p.vy = ad(g, src + 1); p.vz = ad(g, src + 2);
+            p.pt = ad(g, src + 3); p.pf = ad(g, src + 4);
+            p.rx = ad(g, src + 5); p.ry = ad(g, src + 6); p.rz = ad(g, src + 7);
+            p.vx_o = ad(g, dst + 0); p.vy_o = ad(g, dst + 1); p.vz_o = ad(g, dst + 2);
+            p.pt_o = ad(g, dst + 3); p.pf_o = ad(g, dst + 4);
+            p.rx_o = ad(g, dst + 5); p.ry_o = ad(g, dst + 6); p.rz_o = ad(g, dst + 7);
+            p.fox = ad(g, AD_RHS); p.foy = ad(g, AD_RHS + 1); p.foz = ad(g, AD_RHS + 2);
+            p.pto = ad(g, AD_RHS + 3); p.pfo = ad(g, AD_RHS + 4);
+            p.eta = ad(g, AD_CHI); p.kc = kc; p.mus = mus;
+            p.partials = static_cast<double*>(g->ws);
+            e = launch_correction64(g->geom, g->coef, p, chk ? 1 : 0, g->stream);
+            if (e != hipSuccess) return hip_fail(g, e, "adjoint sweep");
+            cp ^= 1;
+            if (chk) {
+                st = reduce_norms(g);
+                if (st != PT_OK) return st;
+                pt_norms nm;
+                st = read_norms(g, &nm);
+                if (st != PT_OK) return st;
+                r = group_rho(nm, ref, ref);
+                if (r <= rtol) break;
+            }
+        }
+    }
+    *lam_copy = cp;
+    if (iters) *iters += it;
+    if (rho) *rho = std::fmax(*rho, r);
+    return (r <= rtol) ? PT_OK : PT_ENOTCONV;
+}
 }  // namespace
 
 pt_status pt_adjoint_workspace_size(const pt_grid* g, int32_t max_sensors, size_t* bytes) {
@@ -732,54 +798,19 @@ pt_status pt_adjoint_stage(pt_grid* g, const int64_t* sensors, int32_t ns, const
     std::vector<double> resid;
     st = misfit_impl(g, sensors, ns, d_obs, &Jv, resid);
     if (st != PT_OK) return st;
-    double gmax = 0.0;
     std::vector<double> seed(ns);
-    for (int32_t s = 0; s < ns; ++s) {
-        seed[s] = -resid[s];           // right-hand side: F_lin(lambda) = J lambda - dJ/dx
-        gmax = std::fmax(gmax, std::fabs(resid[s]));
-    }
+    for (int32_t s = 0; s < ns; ++s) seed[s] = -resid[s];   // -xbar, xbar = dJ/dPf
     const int64_t box_bytes = mx_box(g) * (int64_t)sizeof(double);
-    hipError_t e = hipMemsetAsync(ad(g, 0), 0, 21 * box_bytes, g->stream);
+    hipError_t e = hipMemsetAsync(ad(g, AD_RHS), 0, 5 * box_bytes, g->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(ad_seed(g), seed.data(), ns * sizeof(double), hipMemcpyHostToDevice, g->stream);
-    if (e == hipSuccess) e = launch_scatter(ad_seed(g), ad_offs(g), ns, ad(g, 20), g->stream);
-    if (e == hipSuccess) e = launch_chi64(g->geom, cur(g, PT_ETA), cur(g, PT_LP), ad(g, 21), g->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    if (e == hipSuccess) e = launch_scatter(ad_seed(g), ad_offs(g), ns, ad(g, AD_RHS + 4), g->stream);
+    if (e == hipSuccess) e = launch_chi64(g->geom, cur(g, PT_ETA), cur(g, PT_LP), ad(g, AD_CHI), g->stream);
     if (e != hipSuccess) return hip_fail(g, e, "adjoint set-up");
     int cp = 0;
     int64_t it = 0;
     double r = 0.0;
-    if (gmax > 0.0) {
-        const int64_t nup = g->prm.nup;
-        r = INFINITY;
-        while (it < max_iter) {
-            ++it;
-            const bool chk = (it % nup == 0);
-            SweepPtrs<double> p{};
-            const int src = cp ? 8 : 0, dst = cp ? 0 : 8;
-            p.vx = ad(g, src + 0); p.vy = ad(g, src + 1); p.vz = ad(g, src + 2);
-            p.pt = ad(g, src + 3); p.pf = ad(g, src + 4);
-            p.rx = ad(g, src + 5); p.ry = ad(g, src + 6); p.rz = ad(g, src + 7);
-            p.vx_o = ad(g, dst + 0); p.vy_o = ad(g, dst + 1); p.vz_o = ad(g, dst + 2);
-            p.pt_o = ad(g, dst + 3); p.pf_o = ad(g, dst + 4);
-            p.rx_o = ad(g, dst + 5); p.ry_o = ad(g, dst + 6); p.rz_o = ad(g, dst + 7);
-            p.fox = ad(g, 16); p.foy = ad(g, 17); p.foz = ad(g, 18);
-            p.pto = ad(g, 19); p.pfo = ad(g, 20);
-            p.eta = ad(g, 21); p.kc = cur(g, PT_KC); p.mus = cur(g, PT_MUS);
-            p.partials = static_cast<double*>(g->ws);
-            e = launch_correction64(g->geom, g->coef, p, chk ? 1 : 0, g->stream);
-            if (e != hipSuccess) return hip_fail(g, e, "adjoint sweep");
-            cp ^= 1;
-            if (chk) {
-                st = reduce_norms(g);
-                if (st != PT_OK) return st;
-                pt_norms nm;
-                st = read_norms(g, &nm);
-                if (st != PT_OK) return st;
-                r = group_rho(nm, gmax, gmax);
-                if (r <= rtol) break;
-            }
-        }
-    }
+    st = transposed_solve(g, cur(g, PT_KC), cur(g, PT_MUS), rtol, max_iter, &cp, &it, &r);
+    if (st != PT_OK && st != PT_ENOTCONV) return st;
     e = launch_adjoint_gradient(g->geom, g->coef, cur(g, PT_KC), cur(g, PT_PF), ad(g, (cp ? 8 : 0) + 4),
                                 static_cast<double*>(grad_dev), g->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
@@ -788,6 +819,128 @@ pt_status pt_adjoint_stage(pt_grid* g, const int64_t* sensors, int32_t ns, const
     if (iters) *iters = it;
     if (rho) *rho = r;
     return (r <= rtol) ? PT_OK : PT_ENOTCONV;
+}
+
+pt_status pt_adjoint_tape_size(const pt_grid* g, int32_t n_steps, int32_t n_picard, size_t* bytes) {
+    if (!g || !bytes || n_steps < 1 || n_picard < 1) return PT_EINVAL;
+    *bytes = (size_t)n_steps * (size_t)n_picard * TAPE_NBOX * (size_t)mx_box(g) * sizeof(double);
+    return PT_OK;
+}
+
+pt_status pt_adjoint_run(pt_grid* g, int32_t n_steps, int32_t n_picard, double rtol, double adj_rtol,
+                         int64_t max_iter, const int64_t* sensors, int32_t ns, const double* d_obs, void* tape,
+                         size_t tape_bytes, void* grad_dev, double* J, int64_t* fwd_iters, int64_t* adj_iters) {
+    if (!g || !sensors || !d_obs || !tape || !grad_dev || n_steps < 1 || n_picard < 1 || !(rtol > 0.0) ||
+        !(adj_rtol > 0.0) || max_iter < 1)
+        return PT_EINVAL;
+    pt_status st = check_ready(g);
+    if (st != PT_OK) return st;
+    if (g->prm.flags & (PT_F_POWERLAW | PT_F_DPCAP | PT_F_MECHOFF))
+        return fail(g, PT_EINVAL, "the run adjoint needs the Newtonian viscosity law with mechanics on");
+    if (!(g->prm.flags & PT_F_K0FIELD)) return fail(g, PT_EINVAL, "the run adjoint needs a k0 field");
+    if (!g->aws) return fail(g, PT_EINVAL, "adjoint workspace not bound");
+    if (ns < 1 || ns > g->aws_sensors) return fail(g, PT_EINVAL, "sensor count outside the workspace capacity");
+    size_t need = 0;
+    pt_adjoint_tape_size(g, n_steps, n_picard, &need);
+    if (tape_bytes < need) return fail(g, PT_EINVAL, "tape too small");
+    if ((reinterpret_cast<uintptr_t>(tape) | reinterpret_cast<uintptr_t>(grad_dev)) & 255u)
+        return fail(g, PT_EINVAL, "tape or gradient buffer unaligned");
+    const int64_t box = mx_box(g);
+    double* T = static_cast<double*>(tape);
+    auto tp = [&](int n, int p, int b) { return T + (((int64_t)n * n_picard + p) * TAPE_NBOX + b) * box; };
+    hipError_t e;
+
+    // ---- recorded forward: n_steps Picard steps of n_picard stages ----------
+    int64_t fit = 0;
+    for (int n = 0; n < n_steps; ++n) {
+        st = pt_begin_step(g, n >= 1 ? 1 : 0);
+        if (st != PT_OK) return st;
+        for (int p = 0; p < n_picard; ++p) {
+            st = refresh_impl(g, 1.0, 1.0);
+            if (st != PT_OK) return st;
+            const int rec_in[3] = {PT_LP, PT_KC, PT_ETA};
+            for (int b = 0; b < 3; ++b) {
+                e = launch_copy(cur(g, rec_in[b]), tp(n, p, 5 + b), box, g->stream);
+                if (e != hipSuccess) return hip_fail(g, e, "tape record");
+            }
+            int64_t it = 0;
+            double rho = 0.0;
+            st = pt_solve_linear(g, rtol, max_iter, &it, &rho);
+            fit += it;
+            if (st == PT_ENOTCONV) return fail(g, PT_ENOTCONV, "a forward stage did not reach rtol");
+            if (st != PT_OK) return st;
+            const int rec_out[5] = {PT_VX, PT_VY, PT_VZ, PT_PT, PT_PF};
+            for (int b = 0; b < 5; ++b) {
+                e = launch_copy(cur(g, rec_out[b]), tp(n, p, b), box, g->stream);
+                if (e != hipSuccess) return hip_fail(g, e, "tape record");
+            }
+            st = pt_porosity_step(g);
+            if (st != PT_OK) return st;
+        }
+    }
+    double Jv = 0.0;
+    std::vector<double> resid;
+    st = misfit_impl(g, sensors, ns, d_obs, &Jv, resid);
+    if (st != PT_OK) return st;
+
+    // ---- reverse sweep ---------------------------------------------------------
+    const int64_t box_bytes = box * (int64_t)sizeof(double);
+    e = hipMemsetAsync(ad(g, AD_RHS), 0, (AD_NBOX - AD_RHS) * box_bytes, g->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(grad_dev, 0, box_bytes, g->stream);
+    std::vector<double> seed(ns);
+    for (int32_t s = 0; s < ns; ++s) seed[s] = -resid[s];
+    if (e == hipSuccess) e = hipMemcpyAsync(ad_seed(g), seed.data(), ns * sizeof(double), hipMemcpyHostToDevice, g->stream);
+    if (e == hipSuccess) e = launch_scatter(ad_seed(g), ad_offs(g), ns, ad(g, AD_RHS + 4), g->stream);
+    if (e != hipSuccess) return hip_fail(g, e, "run adjoint set-up");
+    AdjPtrs a{};
+    a.mus = cur(g, PT_MUS);
+    a.rvx = ad(g, AD_RHS); a.rvy = ad(g, AD_RHS + 1); a.rvz = ad(g, AD_RHS + 2);
+    a.rpt = ad(g, AD_RHS + 3); a.rpf = ad(g, AD_RHS + 4);
+    double* lb[2] = {ad(g, AD_LBAR), ad(g, AD_LBAR + 1)};
+    int lin = 0;
+    a.eta_bar = ad(g, AD_ETAB); a.s_bar = ad(g, AD_SB);
+    a.pto_bar = ad(g, AD_OLD); a.pfo_bar = ad(g, AD_OLD + 1); a.lo_bar = ad(g, AD_OLD + 2);
+    a.fbx = ad(g, AD_FB); a.fby = ad(g, AD_FB + 1); a.fbz = ad(g, AD_FB + 2);
+    a.sbxx = ad(g, AD_SO); a.sbyy = ad(g, AD_SO + 1); a.sbzz = ad(g, AD_SO + 2);
+    a.sbxy = ad(g, AD_SO + 3); a.sbxz = ad(g, AD_SO + 4); a.sbyz = ad(g, AD_SO + 5);
+    a.grad = static_cast<double*>(grad_dev);
+    int64_t ait = 0;
+    double arho = 0.0;
+    for (int n = n_steps - 1; n >= 0; --n) {
+        for (int p = n_picard - 1; p >= 0; --p) {
+            a.vx = tp(n, p, 0); a.vy = tp(n, p, 1); a.vz = tp(n, p, 2);
+            a.pt = tp(n, p, 3); a.pf = tp(n, p, 4);
+            a.lp = tp(n, p, 5); a.kc = tp(n, p, 6); a.eta = tp(n, p, 7);
+            a.lbar = lb[lin];
+            a.lbar_out = lb[1 - lin];
+            e = launch_adj_porosity(g->geom, g->coef, a, g->stream);
+            if (e == hipSuccess) e = launch_chi64(g->geom, a.eta, a.lp, ad(g, AD_CHI), g->stream);
+            if (e != hipSuccess) return hip_fail(g, e, "run adjoint porosity");
+            int cp = 0;
+            st = transposed_solve(g, a.kc, a.mus, adj_rtol, max_iter, &cp, &ait, &arho);
+            if (st == PT_ENOTCONV) return fail(g, PT_ENOTCONV, "a transposed stage solve did not reach adj_rtol");
+            if (st != PT_OK) return st;
+            const int lb0 = cp ? 8 : 0;
+            a.lvx = ad(g, lb0); a.lvy = ad(g, lb0 + 1); a.lvz = ad(g, lb0 + 2);
+            a.lpt = ad(g, lb0 + 3); a.lpf = ad(g, lb0 + 4);
+            e = launch_adj_coef(g->geom, g->coef, a, g->stream);
+            if (e != hipSuccess) return hip_fail(g, e, "run adjoint coefficients");
+            lin = 1 - lin;
+        }
+        if (n == 0) break;
+        a.lbar = lb[lin];
+        a.lbar_out = lb[1 - lin];
+        e = launch_adj_step(g->geom, g->coef, a, g->stream);
+        if (e == hipSuccess) e = launch_adj_history(g->geom, g->coef, a, g->stream);
+        if (e != hipSuccess) return hip_fail(g, e, "run adjoint step boundary");
+        lin = 1 - lin;
+    }
+    e = hipStreamSynchronize(g->stream);
+    if (e != hipSuccess) return hip_fail(g, e, "run adjoint");
+    if (J) *J = Jv;
+    if (fwd_iters) *fwd_iters = fit;
+    if (adj_iters) *adj_iters = ait;
+    return PT_OK;
 }
 
 pt_status pt_copy(pt_grid* g, const void* src, void* dst, int64_t n) {

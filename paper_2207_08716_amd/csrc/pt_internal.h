@@ -136,4 +136,28 @@ hipError_t launch_adjoint_gradient(const Geom& g, const Coef& c, const double* k
 hipError_t launch_exp_cells(const Geom& g, const double* src, double* dst, hipStream_t s);
 hipError_t launch_apply_correction(const Geom& g, const MixedPtrs& m, hipStream_t s);
 
+// Adjoint of a Picard run (adjoint_kernels.hip).  rhs holds -xbar, the
+// right-hand side of the transposed stage solve in the slots of the
+// correction sweep (momentum rows on the faces, r_Pt and r_Pf in the cells).
+struct AdjPtrs {
+    // recorded stage (incoming ln(1-phi), coefficients, solution)
+    const double *vx, *vy, *vz, *pt, *pf, *lp, *kc, *eta, *mus;
+    // transposed-solve solution lambda
+    const double *lvx, *lvy, *lvz, *lpt, *lpf;
+    double *rvx, *rvy, *rvz, *rpt, *rpf;   // -xbar
+    const double* lbar;                    // adjoint of the stage's outgoing ln(1-phi)
+    double* lbar_out;                      // adjoint of its incoming ln(1-phi)
+    double *eta_bar, *s_bar;               // porosity-step adjoints of eta and s
+    double *pto_bar, *pfo_bar, *lo_bar;    // adjoints of the step's old values
+    double *fbx, *fby, *fbz;               // adjoint of the history term div(a So)
+    double *sbxx, *sbyy, *sbzz, *sbxy, *sbxz, *sbyz;   // adjoint of the history So
+    double* grad;                          // dJ/d(ln k0), accumulated
+};
+hipError_t launch_adj_porosity(const Geom& g, const Coef& c, const AdjPtrs& a, hipStream_t s);
+hipError_t launch_adj_coef(const Geom& g, const Coef& c, const AdjPtrs& a, hipStream_t s);
+hipError_t launch_adj_step(const Geom& g, const Coef& c, const AdjPtrs& a, hipStream_t s);
+hipError_t launch_adj_history(const Geom& g, const Coef& c, const AdjPtrs& a, hipStream_t s);
+hipError_t launch_absmax5(const Geom& g, const double* const* f, double* partials, int64_t nblocks,
+                          hipStream_t s);
+
 }  // namespace ptk

@@ -1,0 +1,86 @@
+"""Adjoint of a recorded Picard run on the GPU (pt_adjoint_run): against the
+oracle's run adjoint and against central finite differences of the GPU run's
+misfit."""
+import numpy as np
+import pytest
+
+from oracle import adjoint
+from paper_2207_08716_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _problem(n, seed=5, ns=16):
+    cfg = inputs.config_adjoint(n)
+    phi = inputs.porosity_field(cfg)
+    logk0 = np.log(inputs.k0_field(cfg))
+    sensors = inputs.sensor_cells(seed, ns, cfg.shape)
+    return cfg, phi, logk0, sensors
+
+
+def _grid(cfg, phi, logk0):
+    from paper_2207_08716_amd import grid
+    g = grid.Grid(cfg.phys, cfg.nx, cfg.ny, cfg.nz, k0field=True)
+    g.load_initial(phi, np.exp(logk0))
+    g.set_log_k0(logk0)
+    return g
+
+
+def _gpu_run_misfit(g, phi, logk0, sensors, d_obs, steps, stages, rtol):
+    g.reset_state(phi)
+    g.set_log_k0(logk0)
+    for n in range(steps):
+        g.begin_step(n >= 1)
+        for _ in range(stages):
+            g.refresh(1.0, 1.0)
+            it, rho, ok = g.solve_linear(rtol, 2_000_000)
+            assert ok
+            g.porosity_step()
+    return g.misfit(sensors, d_obs)
+
+
+def test_run_adjoint_matches_oracle():
+    n, steps, stages = 12, 2, 2
+    cfg, phi, logk0, sensors = _problem(n)
+    print(f"run adjoint vs oracle n={n} steps={steps} stages={stages}", flush=True)
+    o, _ = adjoint.run_forward(cfg.phys, n, n, n, phi, logk0, steps, stages, 1e-12, record=False)
+    d_obs = o.f["pf"].ravel()[sensors] * 0.8 + 1e-4
+    Jo, grad_o = adjoint.run_adjoint(cfg.phys, n, n, n, phi, logk0, sensors, d_obs, steps, stages,
+                                     1e-12, adj_rtol=1e-12)
+    g = _grid(cfg, phi, logk0)
+    J, grad, fit, ait = g.adjoint_run(sensors, d_obs, steps, stages, rtol=1e-12, adj_rtol=1e-12)
+    grad = grad.cpu().numpy()
+    err = np.abs(grad - grad_o).max() / np.abs(grad_o).max()
+    print("J", J, Jo, "sweeps", fit, ait, "grad rel err", err, flush=True)
+    assert abs(J - Jo) <= 1e-9 * abs(Jo)
+    assert err <= 1e-8
+
+
+def test_run_adjoint_matches_finite_differences():
+    # three steps of three stages at 24^3, solves to 1e-11; central
+    # differences with h = 1e-4 on ln k0 at 6 cells (4 random, 2 sensors)
+    n, steps, stages, rtol = 24, 3, 3, 1e-11
+    cfg, phi, logk0, sensors = _problem(n, seed=6, ns=32)
+    g = _grid(cfg, phi, logk0)
+    J0 = _gpu_run_misfit(g, phi, logk0, sensors, np.zeros(len(sensors)), steps, stages, rtol)
+    d_obs = g.get("pf").ravel()[sensors] * 0.8 + 1e-4
+    g.reset_state(phi)
+    g.set_log_k0(logk0)
+    J, grad, fit, ait = g.adjoint_run(sensors, d_obs, steps, stages, rtol=rtol)
+    grad = grad.cpu().numpy().copy()
+    gmax = np.abs(grad).max()
+    print(f"J {J} sweeps {fit} {ait} max|grad| {gmax}", flush=True)
+    assert gmax > 0
+    rng = np.random.default_rng(7)
+    cells = list(rng.choice(np.arange(n ** 3), size=4, replace=False)) + list(sensors[:2])
+    h = 1e-4
+    for c in cells:
+        vals = []
+        for sgn in (1.0, -1.0):
+            m = logk0.copy().ravel()
+            m[c] += sgn * h
+            vals.append(_gpu_run_misfit(g, phi, m.reshape(logk0.shape), sensors, d_obs, steps, stages, rtol))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        gc = grad.ravel()[c]
+        print("cell", c, gc, fd, flush=True)
+        assert abs(gc - fd) <= 1e-6 * gmax + 1e-6 * abs(fd), (c, gc, fd)
