@@ -272,16 +272,24 @@ pt_status pt_adjoint_stage(pt_grid* g, const int64_t* sensors, int32_t ns, const
  * constant (no derivative).  Needs PT_F_K0FIELD and the Newtonian law (no
  * PT_F_POWERLAW, PT_F_DPCAP, PT_F_MECHOFF), and the adjoint workspace.
  *
- * The tape (caller-owned device buffer, 256-byte aligned, at least
- * pt_adjoint_tape_size bytes) receives every stage's V, Pt, Pf, incoming
- * ln(1-phi), k/mu_f and eta_phi: 8 padded boxes per stage.  grad_dev: one
- * FP64 padded box, overwritten (cells).  On return the grid holds the end
- * state of the run.  Synchronises.  PT_ENOTCONV if a forward or transposed
- * solve misses its tolerance within max_iter (nothing after it is computed). */
-pt_status pt_adjoint_tape_size(const pt_grid* g, int32_t n_steps, int32_t n_picard, size_t* bytes);
-pt_status pt_adjoint_run(pt_grid* g, int32_t n_steps, int32_t n_picard, double rtol, double adj_rtol,
-                         int64_t max_iter, const int64_t* sensors, int32_t ns, const double* d_obs, void* tape,
-                         size_t tape_bytes, void* grad_dev, double* J, int64_t* fwd_iters, int64_t* adj_iters);
+ * The tape is a caller-owned device buffer, 256-byte aligned, of at least
+ * pt_adjoint_tape_size bytes.  checkpoint = 0: it receives every stage's V,
+ * Pt, Pf, incoming ln(1-phi), k/mu_f and eta_phi (8 padded boxes per stage;
+ * n_steps * n_picard * 8 boxes).  checkpoint = 1: it keeps each step's start
+ * state (V, Pt, Pf, ln(1-phi), R, stress history: 15 boxes per step) plus
+ * one step's stages (n_picard * 8 boxes); the reverse sweep recomputes each
+ * step from its checkpoint, bitwise the recorded run, at the cost of a
+ * second forward pass.  grad_dev: one FP64 padded box, overwritten (cells).
+ * On return the grid holds the end state of the run (checkpoint = 0) or of
+ * its first step (checkpoint = 1).  Synchronises.  PT_ENOTCONV if a forward
+ * or transposed solve misses its tolerance within max_iter (nothing after
+ * it is computed). */
+pt_status pt_adjoint_tape_size(const pt_grid* g, int32_t n_steps, int32_t n_picard, int32_t checkpoint,
+                               size_t* bytes);
+pt_status pt_adjoint_run(pt_grid* g, int32_t n_steps, int32_t n_picard, int32_t checkpoint, double rtol,
+                         double adj_rtol, int64_t max_iter, const int64_t* sensors, int32_t ns, const double* d_obs,
+                         void* tape, size_t tape_bytes, void* grad_dev, double* J, int64_t* fwd_iters,
+                         int64_t* adj_iters);
 
 /* Streaming copy of n doubles (achievable-bandwidth reference). */
 pt_status pt_copy(pt_grid* g, const void* src, void* dst, int64_t n);

@@ -99,8 +99,8 @@ def load(path: str = LIB_PATH):
     lib.pt_misfit.argtypes = [vp, P(C.c_int64), C.c_int32, P(C.c_double), P(C.c_double)]
     lib.pt_adjoint_stage.argtypes = [vp, P(C.c_int64), C.c_int32, P(C.c_double), C.c_double, C.c_int64, vp,
                                      P(C.c_double), P(C.c_int64), P(C.c_double)]
-    lib.pt_adjoint_tape_size.argtypes = [vp, C.c_int32, C.c_int32, P(C.c_size_t)]
-    lib.pt_adjoint_run.argtypes = [vp, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_int64,
+    lib.pt_adjoint_tape_size.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, P(C.c_size_t)]
+    lib.pt_adjoint_run.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_int64,
                                    P(C.c_int64), C.c_int32, P(C.c_double), vp, C.c_size_t, vp,
                                    P(C.c_double), P(C.c_int64), P(C.c_int64)]
     lib.pt_status_str.argtypes = [C.c_int]

@@ -1,9 +1,15 @@
-"""torch.autograd.Function over the stage adjoint.
+"""torch.autograd.Functions over the hand-written adjoints.
 
 LogKMisfit.apply(logk0, problem) runs one linear Picard stage from the
 problem's initial state with k0 = exp(logk0) and returns the sensor misfit
-J = 1/2 sum_s (Pf_s - d_s)^2; backward returns dJ/d(logk0) from the
-hand-written adjoint (pt_adjoint_stage).  Every step runs in the HIP library.
+J = 1/2 sum_s (Pf_s - d_s)^2; backward returns dJ/d(logk0) from the stage
+adjoint (pt_adjoint_stage).
+
+LogKMisfitRun.apply(logk0, run_problem) does the same for a run of Picard
+steps x stages (pt_adjoint_run: recorded forward, then the reverse sweep; the
+gradient is computed with the forward and kept for backward).
+
+Every step runs in the HIP library.
 """
 from __future__ import annotations
 
@@ -47,3 +53,42 @@ class LogKMisfit(torch.autograd.Function):
         if not ok:
             raise RuntimeError("adjoint solve did not converge")
         return grad_out * grad.clone(), None
+
+
+class RunProblem:
+    """A Grid plus the data of a Picard-run misfit problem."""
+
+    def __init__(self, grid, phi, sensors, d_obs, n_steps, n_picard, rtol=1e-11, adj_rtol=None,
+                 max_iter=2_000_000, checkpoint=False):
+        self.grid = grid
+        self.phi = phi
+        self.sensors = sensors
+        self.d_obs = d_obs
+        self.n_steps = n_steps
+        self.n_picard = n_picard
+        self.rtol = rtol
+        self.adj_rtol = rtol if adj_rtol is None else adj_rtol
+        self.max_iter = max_iter
+        self.checkpoint = checkpoint
+
+    def forward(self, logk0):
+        """(J, dJ/dlogk0 as a new device tensor) of the run from the initial state."""
+        g = self.grid
+        g.reset_state(self.phi)
+        g.set_log_k0(logk0)
+        J, grad, _fit, _ait = g.adjoint_run(self.sensors, self.d_obs, self.n_steps, self.n_picard, self.rtol,
+                                            self.adj_rtol, self.max_iter, self.checkpoint)
+        return J, grad.clone()
+
+
+class LogKMisfitRun(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, logk0: torch.Tensor, problem: RunProblem):
+        J, grad = problem.forward(logk0.detach())
+        ctx.save_for_backward(grad)
+        return logk0.new_tensor(J)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (grad,) = ctx.saved_tensors
+        return grad_out * grad, None

@@ -821,15 +821,78 @@ pt_status pt_adjoint_stage(pt_grid* g, const int64_t* sensors, int32_t ns, const
     return (r <= rtol) ? PT_OK : PT_ENOTCONV;
 }
 
-pt_status pt_adjoint_tape_size(const pt_grid* g, int32_t n_steps, int32_t n_picard, size_t* bytes) {
-    if (!g || !bytes || n_steps < 1 || n_picard < 1) return PT_EINVAL;
-    *bytes = (size_t)n_steps * (size_t)n_picard * TAPE_NBOX * (size_t)mx_box(g) * sizeof(double);
+}  // extern "C"
+
+namespace {
+// Fields that restart a step exactly: V, Pt, Pf, ln(1-phi), damped residual
+// R, stress history.  Old values, Fo and the coefficients are recomputed by
+// the step set-up and the refresh (no relaxation, Newtonian law).
+constexpr int CKPT_FIELDS[] = {PT_VX, PT_VY, PT_VZ, PT_PT, PT_PF, PT_LP, PT_RX, PT_RY, PT_RZ,
+                               PT_SXX, PT_SYY, PT_SZZ, PT_SXY, PT_SXZ, PT_SYZ};
+constexpr int CKPT_NBOX = sizeof(CKPT_FIELDS) / sizeof(CKPT_FIELDS[0]);
+
+size_t tape_boxes(int32_t n_steps, int32_t n_picard, int32_t checkpoint) {
+    return checkpoint ? (size_t)n_steps * CKPT_NBOX + (size_t)n_picard * TAPE_NBOX
+                      : (size_t)n_steps * n_picard * TAPE_NBOX;
+}
+
+// One Picard step from the present state, recording its stages at rec(p, b).
+template <typename Rec>
+pt_status recorded_step(pt_grid* g, int n, int32_t n_picard, double rtol, int64_t max_iter, Rec rec,
+                        int64_t* fit) {
+    const int64_t box = mx_box(g);
+    pt_status st = pt_begin_step(g, n >= 1 ? 1 : 0);
+    if (st != PT_OK) return st;
+    for (int p = 0; p < n_picard; ++p) {
+        st = refresh_impl(g, 1.0, 1.0);
+        if (st != PT_OK) return st;
+        const int rec_in[3] = {PT_LP, PT_KC, PT_ETA};
+        for (int b = 0; b < 3; ++b) {
+            hipError_t e = launch_copy(cur(g, rec_in[b]), rec(p, 5 + b), box, g->stream);
+            if (e != hipSuccess) return hip_fail(g, e, "tape record");
+        }
+        int64_t it = 0;
+        double rho = 0.0;
+        st = pt_solve_linear(g, rtol, max_iter, &it, &rho);
+        *fit += it;
+        if (st == PT_ENOTCONV) return fail(g, PT_ENOTCONV, "a forward stage did not reach rtol");
+        if (st != PT_OK) return st;
+        const int rec_out[5] = {PT_VX, PT_VY, PT_VZ, PT_PT, PT_PF};
+        for (int b = 0; b < 5; ++b) {
+            hipError_t e = launch_copy(cur(g, rec_out[b]), rec(p, b), box, g->stream);
+            if (e != hipSuccess) return hip_fail(g, e, "tape record");
+        }
+        st = pt_porosity_step(g);
+        if (st != PT_OK) return st;
+    }
     return PT_OK;
 }
 
-pt_status pt_adjoint_run(pt_grid* g, int32_t n_steps, int32_t n_picard, double rtol, double adj_rtol,
-                         int64_t max_iter, const int64_t* sensors, int32_t ns, const double* d_obs, void* tape,
-                         size_t tape_bytes, void* grad_dev, double* J, int64_t* fwd_iters, int64_t* adj_iters) {
+// Copy the present state into (save) or out of (restore) a step checkpoint.
+pt_status checkpoint_copy(pt_grid* g, double* ck, bool save) {
+    const int64_t box = mx_box(g);
+    for (int b = 0; b < CKPT_NBOX; ++b) {
+        double* f = cur(g, CKPT_FIELDS[b]);
+        hipError_t e = save ? launch_copy(f, ck + b * box, box, g->stream) : launch_copy(ck + b * box, f, box, g->stream);
+        if (e != hipSuccess) return hip_fail(g, e, "checkpoint");
+    }
+    return PT_OK;
+}
+}  // namespace
+
+extern "C" {
+
+pt_status pt_adjoint_tape_size(const pt_grid* g, int32_t n_steps, int32_t n_picard, int32_t checkpoint,
+                               size_t* bytes) {
+    if (!g || !bytes || n_steps < 1 || n_picard < 1) return PT_EINVAL;
+    *bytes = tape_boxes(n_steps, n_picard, checkpoint) * (size_t)mx_box(g) * sizeof(double);
+    return PT_OK;
+}
+
+pt_status pt_adjoint_run(pt_grid* g, int32_t n_steps, int32_t n_picard, int32_t checkpoint, double rtol,
+                         double adj_rtol, int64_t max_iter, const int64_t* sensors, int32_t ns, const double* d_obs,
+                         void* tape, size_t tape_bytes, void* grad_dev, double* J, int64_t* fwd_iters,
+                         int64_t* adj_iters) {
     if (!g || !sensors || !d_obs || !tape || !grad_dev || n_steps < 1 || n_picard < 1 || !(rtol > 0.0) ||
         !(adj_rtol > 0.0) || max_iter < 1)
         return PT_EINVAL;
@@ -841,42 +904,34 @@ pt_status pt_adjoint_run(pt_grid* g, int32_t n_steps, int32_t n_picard, double r
     if (!g->aws) return fail(g, PT_EINVAL, "adjoint workspace not bound");
     if (ns < 1 || ns > g->aws_sensors) return fail(g, PT_EINVAL, "sensor count outside the workspace capacity");
     size_t need = 0;
-    pt_adjoint_tape_size(g, n_steps, n_picard, &need);
+    pt_adjoint_tape_size(g, n_steps, n_picard, checkpoint, &need);
     if (tape_bytes < need) return fail(g, PT_EINVAL, "tape too small");
     if ((reinterpret_cast<uintptr_t>(tape) | reinterpret_cast<uintptr_t>(grad_dev)) & 255u)
         return fail(g, PT_EINVAL, "tape or gradient buffer unaligned");
     const int64_t box = mx_box(g);
     double* T = static_cast<double*>(tape);
-    auto tp = [&](int n, int p, int b) { return T + (((int64_t)n * n_picard + p) * TAPE_NBOX + b) * box; };
+    // all stages: stage (n, p) at T[(n P + p) 8 boxes]; checkpoints: step n's
+    // start state at T[n 15 boxes], then one step's stages after them
+    double* step_tape = T + (int64_t)n_steps * CKPT_NBOX * box;
+    auto tp = [&](int n, int p, int b) {
+        if (checkpoint) return step_tape + ((int64_t)p * TAPE_NBOX + b) * box;
+        return T + (((int64_t)n * n_picard + p) * TAPE_NBOX + b) * box;
+    };
     hipError_t e;
 
     // ---- recorded forward: n_steps Picard steps of n_picard stages ----------
     int64_t fit = 0;
+    // whether a refresh preceded each step (the first refresh of a handle
+    // takes the new coefficients without the relaxation formula)
+    std::vector<char> refreshed_at(n_steps, 0);
     for (int n = 0; n < n_steps; ++n) {
-        st = pt_begin_step(g, n >= 1 ? 1 : 0);
-        if (st != PT_OK) return st;
-        for (int p = 0; p < n_picard; ++p) {
-            st = refresh_impl(g, 1.0, 1.0);
+        if (checkpoint) {
+            st = checkpoint_copy(g, T + (int64_t)n * CKPT_NBOX * box, true);
             if (st != PT_OK) return st;
-            const int rec_in[3] = {PT_LP, PT_KC, PT_ETA};
-            for (int b = 0; b < 3; ++b) {
-                e = launch_copy(cur(g, rec_in[b]), tp(n, p, 5 + b), box, g->stream);
-                if (e != hipSuccess) return hip_fail(g, e, "tape record");
-            }
-            int64_t it = 0;
-            double rho = 0.0;
-            st = pt_solve_linear(g, rtol, max_iter, &it, &rho);
-            fit += it;
-            if (st == PT_ENOTCONV) return fail(g, PT_ENOTCONV, "a forward stage did not reach rtol");
-            if (st != PT_OK) return st;
-            const int rec_out[5] = {PT_VX, PT_VY, PT_VZ, PT_PT, PT_PF};
-            for (int b = 0; b < 5; ++b) {
-                e = launch_copy(cur(g, rec_out[b]), tp(n, p, b), box, g->stream);
-                if (e != hipSuccess) return hip_fail(g, e, "tape record");
-            }
-            st = pt_porosity_step(g);
-            if (st != PT_OK) return st;
+            refreshed_at[n] = g->refreshed ? 1 : 0;
         }
+        st = recorded_step(g, n, n_picard, rtol, max_iter, [&](int p, int b) { return tp(n, p, b); }, &fit);
+        if (st != PT_OK) return st;
     }
     double Jv = 0.0;
     std::vector<double> resid;
@@ -907,6 +962,15 @@ pt_status pt_adjoint_run(pt_grid* g, int32_t n_steps, int32_t n_picard, double r
     int64_t ait = 0;
     double arho = 0.0;
     for (int n = n_steps - 1; n >= 0; --n) {
+        if (checkpoint && n < n_steps - 1) {
+            // recompute step n from its checkpoint (bitwise the recorded run)
+            st = checkpoint_copy(g, T + (int64_t)n * CKPT_NBOX * box, false);
+            if (st != PT_OK) return st;
+            g->refreshed = refreshed_at[n] != 0;
+            int64_t rit = 0;
+            st = recorded_step(g, n, n_picard, rtol, max_iter, [&](int p, int b) { return tp(n, p, b); }, &rit);
+            if (st != PT_OK) return st;
+        }
         for (int p = n_picard - 1; p >= 0; --p) {
             a.vx = tp(n, p, 0); a.vy = tp(n, p, 1); a.vz = tp(n, p, 2);
             a.pt = tp(n, p, 3); a.pf = tp(n, p, 4);

@@ -271,15 +271,19 @@ class Grid:
             C.c_void_p(self.grad_buf.data_ptr()), C.byref(J), C.byref(it), C.byref(rho)), "adjoint_stage")
         return J.value, self.grad_buf[:self.nz, :self.ny, :self.nx], it.value, rho.value, st == 0
 
-    def adjoint_run(self, sensors, d_obs, n_steps, n_picard, rtol=1e-12, adj_rtol=None, max_iter=2_000_000):
+    def adjoint_run(self, sensors, d_obs, n_steps, n_picard, rtol=1e-12, adj_rtol=None, max_iter=2_000_000,
+                    checkpoint=False):
         """Recorded Picard run of n_steps x n_picard stages from the present
         state and its adjoint (see pt_adjoint_run): returns J, dJ/d(ln k0)
-        (device tensor view, cells), forward and transposed sweep counts."""
+        (device tensor view, cells), forward and transposed sweep counts.
+        checkpoint: keep step checkpoints and recompute the stages in reverse."""
         adj_rtol = rtol if adj_rtol is None else adj_rtol
         self.enable_adjoint(max(64, len(sensors)))
         nbytes = C.c_size_t()
-        _check(self.lib, self.h, self.lib.pt_adjoint_tape_size(self.h, int(n_steps), int(n_picard), C.byref(nbytes)),
+        _check(self.lib, self.h, self.lib.pt_adjoint_tape_size(self.h, int(n_steps), int(n_picard),
+                                                               int(bool(checkpoint)), C.byref(nbytes)),
                "tape size")
+        self.tape_bytes = nbytes.value
         with torch.cuda.stream(self.stream):
             tape = torch.empty((nbytes.value + 7) // 8, dtype=torch.float64, device=self.device)
         s_arr = np.ascontiguousarray(sensors, dtype=np.int64)
@@ -288,7 +292,7 @@ class Grid:
         fit = C.c_int64()
         ait = C.c_int64()
         st = _check(self.lib, self.h, self.lib.pt_adjoint_run(
-            self.h, int(n_steps), int(n_picard), float(rtol), float(adj_rtol), int(max_iter),
+            self.h, int(n_steps), int(n_picard), int(bool(checkpoint)), float(rtol), float(adj_rtol), int(max_iter),
             s_arr.ctypes.data_as(C.POINTER(C.c_int64)), len(s_arr), d_arr.ctypes.data_as(C.POINTER(C.c_double)),
             C.c_void_p(tape.data_ptr()), nbytes.value, C.c_void_p(self.grad_buf.data_ptr()),
             C.byref(J), C.byref(fit), C.byref(ait)), "adjoint_run")
