@@ -155,6 +155,66 @@ def time_to_tol(n: int, rtol: float = 1e-8, n_picard: int = 5, eta_in: float = 1
     return out
 
 
+def fp32_sweep_time(g, k_lo=45, k_hi=165):
+    """Average FP32 correction sweep (mixed-precision inner iteration) time:
+    two defect-correction calls with exactly k_lo and k_hi inner sweeps
+    (inner tolerance unreachable), differenced so that the FP64 residual,
+    set-up and correction kernels cancel."""
+    import torch
+    g.enable_mixed()
+    g.solve_mixed(1e-300, 1e-30, 15, 1)          # first call clears the workspace
+    torch.cuda.synchronize()
+    ts = []
+    for k in (k_lo, k_hi):
+        g.set_residual_reference(None)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.solve_mixed(1e-300, 1e-30, k, 1)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    return (ts[1] - ts[0]) / (k_hi - k_lo)
+
+
+def adjoint_measure(n, n_steps=10, n_picard=5, rtol=1e-10, ns=64, checkpoint=False):
+    """Wall time of the recorded Picard run and its adjoint (pt_adjoint_run)
+    on the adjoint workload at n^3: n_steps steps of n_picard stages, forward
+    and transposed solves to rtol, ns sensors, observations d = 0."""
+    import numpy as np
+    import torch
+    from paper_2207_08716_amd import inputs, schedules
+
+    cfg = inputs.config_adjoint(n)
+    f = inputs.initial_fields(cfg)
+    sensors = inputs.sensor_cells(5, ns, cfg.shape)
+    g = schedules.make_grid(cfg, f)
+    g.set_log_k0(np.log(f["k0"]))
+    marks = []
+
+    def progress(phase, step, stage, sweeps):
+        marks.append((phase, time.perf_counter()))
+        print(f"adjoint run n={n}: {phase} step {step} stage {stage}: {sweeps} sweeps",
+              file=sys.stderr, flush=True)
+    g.set_progress(progress)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J, grad, fit, ait = g.adjoint_run(sensors, np.zeros(ns), n_steps, n_picard, rtol, rtol,
+                                      checkpoint=checkpoint)
+    t1 = time.perf_counter()
+    t_fwd = max(t for ph, t in marks if ph == "forward") - t0
+    out = {"n": n, "steps": n_steps, "picard_stages": n_picard, "rtol": rtol, "sensors": ns,
+           "checkpoint": bool(checkpoint), "J": J, "max_abs_grad": float(grad.abs().max()),
+           "forward_s": round(t_fwd, 3), "reverse_s": round(t1 - t0 - t_fwd, 3),
+           "forward_sweeps": fit, "transposed_sweeps": ait,
+           "tape_gb": round(g.tape_bytes / 1e9, 3),
+           "workload": f"{n}^3 porosity anomaly, ln k0 Gaussian random field (sigma 0.5), "
+                       f"{n_steps} steps x {n_picard} Picard stages, observations 0"}
+    g.set_progress(None)
+    g.close()
+    del g
+    torch.cuda.empty_cache()
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -165,6 +225,12 @@ def main(argv=None):
     ap.add_argument("--cpu-iters", type=int, default=2)
     ap.add_argument("--ttt-n", type=int, default=127,
                     help="grid size of the mixed-vs-FP64 time-to-tolerance comparison (0: skip)")
+    ap.add_argument("--adjoint-n", type=int, default=0,
+                    help="grid size of the run-adjoint measurement, 10 steps x 5 stages (0: skip)")
+    ap.add_argument("--adjoint-steps", type=int, default=10, help="physical steps of the adjoint run")
+    ap.add_argument("--adjoint-stages", type=int, default=5, help="Picard stages per step of the adjoint run")
+    ap.add_argument("--adjoint-checkpoint", action="store_true",
+                    help="run the adjoint measurement with step checkpoints")
     args = ap.parse_args(argv)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -217,6 +283,10 @@ def main(argv=None):
     # linear (Picard-stage) variant of the sweep: porosity frozen
     t_lin = timed(lambda k: [g.iteration(update_lp=False, norms=False) for _ in range(k)], k_reps) / k_reps
 
+    # ---- FP32 correction sweep of the mixed-precision solver ---------------
+    t_f32 = fp32_sweep_time(g)
+    a_eff32 = teff.a_eff_bytes(cfg.ncell, 4)
+
     # ---- achievable HBM bandwidth: streaming copy of one field --------------
     src = g.buf["kc"][0].view(-1)
     dst = g.ws.new_empty(src.numel())
@@ -250,7 +320,7 @@ def main(argv=None):
         "pct_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2),
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_iter<update_lp=true,norms=false> (fused PT sweep)",
+            "kernel": "k_sweep<double, THESIS, norms=false> (fused PT sweep)",
             "achieved": round(achieved, 2),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -261,6 +331,10 @@ def main(argv=None):
         },
         "linear_sweep": {"t_it_ms": round(t_lin * 1e3, 4),
                          "t_eff_gbs": round(a_eff / t_lin / 1e9, 2)},
+        "fp32_correction_sweep": {"t_it_ms": round(t_f32 * 1e3, 4),
+                                  "t_eff_gbs": round(a_eff32 / t_f32 / 1e9, 2),
+                                  "frac": round(a_eff32 / t_f32 / 1e9 / HBM_PEAK_GBS, 4),
+                                  "algorithmic_bytes_per_launch": a_eff32},
         "copy_gbs": round(copy_gbs, 1),
         "wall_s_timed": round(t_wall, 3),
         "norms_last_check": norms,
@@ -271,6 +345,9 @@ def main(argv=None):
     torch.cuda.empty_cache()
 
     out["time_to_tol"] = time_to_tol(args.ttt_n) if args.ttt_n > 0 else None
+    if args.adjoint_n > 0:
+        out["adjoint_run"] = adjoint_measure(args.adjoint_n, args.adjoint_steps, args.adjoint_stages,
+                                             checkpoint=args.adjoint_checkpoint)
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, fields, args.cpu_iters)

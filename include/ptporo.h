@@ -149,6 +149,17 @@ pt_status pt_bind_workspace(pt_grid* g, void* dev_ptr, size_t bytes);
 
 /* Stream for all launches (a hipStream_t; NULL = the null stream). */
 pt_status pt_set_stream(pt_grid* g, void* hip_stream);
+
+/* Progress report of long calls (pt_adjoint_run): fn(user, phase, step,
+ * stage, sweeps) is called on the calling thread after every stage, with
+ * phase PT_PROGRESS_FORWARD (recorded forward), PT_PROGRESS_RECOMPUTE
+ * (a checkpointed step recomputed) or PT_PROGRESS_REVERSE (a transposed
+ * stage solve), and the stage's sweep count.  fn = NULL: no reports. */
+#define PT_PROGRESS_FORWARD 0
+#define PT_PROGRESS_REVERSE 1
+#define PT_PROGRESS_RECOMPUTE 2
+typedef void (*pt_progress_fn)(void* user, int32_t phase, int32_t step, int32_t stage, int64_t sweeps);
+pt_status pt_set_progress(pt_grid* g, pt_progress_fn fn, void* user);
 pt_status pt_set_params(pt_grid* g, const pt_params* params);
 
 /* Which copy (0/1) of a double-buffered field holds the present state. */

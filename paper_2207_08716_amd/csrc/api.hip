@@ -31,6 +31,8 @@ struct pt_grid {
     bool ref_set = false;
     bool refreshed = false;    // any refresh done on this handle
     bool norms_pending = false;
+    pt_progress_fn progress = nullptr;   // per-stage report of long calls
+    void* progress_user = nullptr;
     std::string err;
 };
 
@@ -337,6 +339,13 @@ pt_status pt_bind_workspace(pt_grid* g, void* dev_ptr, size_t bytes) {
     if (!dev_ptr || bytes < ws_needed(g)) return fail(g, PT_EINVAL, "workspace missing or too small");
     g->ws = dev_ptr;
     g->ws_bytes = bytes;
+    return PT_OK;
+}
+
+pt_status pt_set_progress(pt_grid* g, pt_progress_fn fn, void* user) {
+    if (!g) return PT_EINVAL;
+    g->progress = fn;
+    g->progress_user = user;
     return PT_OK;
 }
 
@@ -839,7 +848,7 @@ size_t tape_boxes(int32_t n_steps, int32_t n_picard, int32_t checkpoint) {
 // One Picard step from the present state, recording its stages at rec(p, b).
 template <typename Rec>
 pt_status recorded_step(pt_grid* g, int n, int32_t n_picard, double rtol, int64_t max_iter, Rec rec,
-                        int64_t* fit) {
+                        int64_t* fit, int32_t phase) {
     const int64_t box = mx_box(g);
     pt_status st = pt_begin_step(g, n >= 1 ? 1 : 0);
     if (st != PT_OK) return st;
@@ -864,6 +873,7 @@ pt_status recorded_step(pt_grid* g, int n, int32_t n_picard, double rtol, int64_
         }
         st = pt_porosity_step(g);
         if (st != PT_OK) return st;
+        if (g->progress) g->progress(g->progress_user, phase, n, p, it);
     }
     return PT_OK;
 }
@@ -930,7 +940,8 @@ pt_status pt_adjoint_run(pt_grid* g, int32_t n_steps, int32_t n_picard, int32_t 
             if (st != PT_OK) return st;
             refreshed_at[n] = g->refreshed ? 1 : 0;
         }
-        st = recorded_step(g, n, n_picard, rtol, max_iter, [&](int p, int b) { return tp(n, p, b); }, &fit);
+        st = recorded_step(g, n, n_picard, rtol, max_iter, [&](int p, int b) { return tp(n, p, b); }, &fit,
+                           PT_PROGRESS_FORWARD);
         if (st != PT_OK) return st;
     }
     double Jv = 0.0;
@@ -968,7 +979,8 @@ pt_status pt_adjoint_run(pt_grid* g, int32_t n_steps, int32_t n_picard, int32_t 
             if (st != PT_OK) return st;
             g->refreshed = refreshed_at[n] != 0;
             int64_t rit = 0;
-            st = recorded_step(g, n, n_picard, rtol, max_iter, [&](int p, int b) { return tp(n, p, b); }, &rit);
+            st = recorded_step(g, n, n_picard, rtol, max_iter, [&](int p, int b) { return tp(n, p, b); }, &rit,
+                               PT_PROGRESS_RECOMPUTE);
             if (st != PT_OK) return st;
         }
         for (int p = n_picard - 1; p >= 0; --p) {
@@ -981,6 +993,7 @@ pt_status pt_adjoint_run(pt_grid* g, int32_t n_steps, int32_t n_picard, int32_t 
             if (e == hipSuccess) e = launch_chi64(g->geom, a.eta, a.lp, ad(g, AD_CHI), g->stream);
             if (e != hipSuccess) return hip_fail(g, e, "run adjoint porosity");
             int cp = 0;
+            const int64_t ait0 = ait;
             st = transposed_solve(g, a.kc, a.mus, adj_rtol, max_iter, &cp, &ait, &arho);
             if (st == PT_ENOTCONV) return fail(g, PT_ENOTCONV, "a transposed stage solve did not reach adj_rtol");
             if (st != PT_OK) return st;
@@ -990,6 +1003,7 @@ pt_status pt_adjoint_run(pt_grid* g, int32_t n_steps, int32_t n_picard, int32_t 
             e = launch_adj_coef(g->geom, g->coef, a, g->stream);
             if (e != hipSuccess) return hip_fail(g, e, "run adjoint coefficients");
             lin = 1 - lin;
+            if (g->progress) g->progress(g->progress_user, PT_PROGRESS_REVERSE, n, p, ait - ait0);
         }
         if (n == 0) break;
         a.lbar = lb[lin];

@@ -271,6 +271,19 @@ class Grid:
             C.c_void_p(self.grad_buf.data_ptr()), C.byref(J), C.byref(it), C.byref(rho)), "adjoint_stage")
         return J.value, self.grad_buf[:self.nz, :self.ny, :self.nx], it.value, rho.value, st == 0
 
+    def set_progress(self, fn):
+        """fn(phase_name, step, stage, sweeps) after every stage of long calls
+        (None: off)."""
+        if fn is None:
+            self._progress_cb = None
+            _check(self.lib, self.h, self.lib.pt_set_progress(self.h, abi.PROGRESS_FN(), None), "progress")
+            return
+
+        def cb(_user, phase, step, stage, sweeps):
+            fn(abi.PROGRESS_PHASE.get(phase, str(phase)), step, stage, sweeps)
+        self._progress_cb = abi.PROGRESS_FN(cb)     # kept alive with the grid
+        _check(self.lib, self.h, self.lib.pt_set_progress(self.h, self._progress_cb, None), "progress")
+
     def adjoint_run(self, sensors, d_obs, n_steps, n_picard, rtol=1e-12, adj_rtol=None, max_iter=2_000_000,
                     checkpoint=False):
         """Recorded Picard run of n_steps x n_picard stages from the present
