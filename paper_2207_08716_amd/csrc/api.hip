@@ -182,7 +182,7 @@ pt_status check_ready(pt_grid* g) {
 // Workspace layout (doubles): [partials: n_blocks * 8][norms: 8][pad to 256 B]
 // [three padded-box scratch fields for the refresh passes].
 int64_t ws_scratch_offset(const pt_grid* g) {
-    const int64_t head = iter_grid_blocks(g->geom) * NNORM + NNORM;
+    const int64_t head = norm_blocks(g->geom) * NNORM + NNORM;
     return (head + 31) / 32 * 32;
 }
 
@@ -218,7 +218,7 @@ SweepPtrs<double> sweep_ptrs(pt_grid* g) {
 }
 
 pt_status reduce_norms(pt_grid* g) {
-    const int64_t nb = iter_grid_blocks(g->geom);
+    const int64_t nb = norm_blocks(g->geom);
     double* out = static_cast<double*>(g->ws) + nb * NNORM;
     hipError_t e = launch_reduce_max(static_cast<double*>(g->ws), nb, out, g->stream);
     if (e != hipSuccess) return hip_fail(g, e, "reduce");
@@ -254,7 +254,7 @@ size_t mx_needed(const pt_grid* g) { return (size_t)(MX_NBOX * mx_box(g)) * size
 float* mx(pt_grid* g, int b) { return g->mws + (int64_t)b * mx_box(g); }
 
 pt_status read_norms(pt_grid* g, pt_norms* out) {
-    const int64_t nb = iter_grid_blocks(g->geom);
+    const int64_t nb = norm_blocks(g->geom);
     double host[NNORM];
     hipError_t e = hipMemcpyAsync(host, static_cast<double*>(g->ws) + nb * NNORM, sizeof(host),
                                   hipMemcpyDeviceToHost, g->stream);
@@ -710,7 +710,7 @@ pt_status transposed_solve(pt_grid* g, const double* kc, const double* mus, doub
     const int64_t box_bytes = mx_box(g) * (int64_t)sizeof(double);
     hipError_t e = hipMemsetAsync(ad(g, 0), 0, 16 * box_bytes, g->stream);
     if (e != hipSuccess) return hip_fail(g, e, "adjoint clear");
-    const int64_t nb = iter_grid_blocks(g->geom);
+    const int64_t nb = norm_blocks(g->geom);
     const double* rhs[5] = {ad(g, AD_RHS), ad(g, AD_RHS + 1), ad(g, AD_RHS + 2), ad(g, AD_RHS + 3), ad(g, AD_RHS + 4)};
     e = launch_absmax5(g->geom, rhs, static_cast<double*>(g->ws), nb, g->stream);
     if (e != hipSuccess) return hip_fail(g, e, "rhs norm");

@@ -33,13 +33,21 @@ namespace ptk {
 
 namespace {
 
-template <typename T>
+template <typename T, int W>
 struct Lds {
-    T vx[BY][BX], vy[BY][BX], vz1[BY][BX];
-    T pf[BY][BX], kc[BY][BX], s[BY][BX], mu[BY][BX], mu1[BY][BX];
-    T ptn[BY][BX], txx[BY][BX], tyy[BY][BX], txy[BY][BX], w[BY][BX];
-    T txz[2][BY][BX], tyz[2][BY][BX];
+    T vx[BY][W], vy[BY][W], vz1[BY][W];
+    T pf[BY][W], kc[BY][W], s[BY][W], mu[BY][W], mu1[BY][W];
+    T ptn[BY][W], txx[BY][W], tyy[BY][W], txy[BY][W], w[BY][W];
+    T txz[2][BY][W], tyz[2][BY][W];
 };
+
+// Block width of a sweep variant: the plain sweeps use BX (64-column output
+// tiles), the variants that also reduce norms BX_NORMS (whole waves for the
+// shuffle reduction, and 8 waves, which leaves them 256 registers).
+template <int MODE, bool NORMS>
+constexpr int sweep_bx() {
+    return (NORMS || MODE == MD_RESID) ? BX_NORMS : BX;
+}
 
 template <typename T>
 __device__ __forceinline__ T nanmax(T m, T v) {
@@ -72,16 +80,17 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t L, int64_t total) {
 }
 
 template <typename T, int MODE, bool NORMS>
-__global__ __launch_bounds__(BX * BY) void k_sweep(Geom g, Coef cd, SweepPtrs<T> p) {
+__global__ __launch_bounds__((sweep_bx<MODE, NORMS>() * BY)) void k_sweep(Geom g, Coef cd, SweepPtrs<T> p) {
+    constexpr int W = sweep_bx<MODE, NORMS>();
     constexpr bool UPD_LP = (MODE == MD_THESIS);
     constexpr bool RESID = (MODE == MD_RESID);
     constexpr bool CORR = (MODE == MD_CORR);
     constexpr bool WNORM = NORMS || RESID;
-    __shared__ Lds<T> sh;
+    __shared__ Lds<T, W> sh;
     const CT<T> c(cd);
     const T zero = T(0), half = T(0.5), one = T(1), two = T(2), quarter = T(0.25);
 
-    const int gx = (g.nx + BX - 3) / (BX - 2);
+    const int gx = (g.nx + W - 3) / (W - 2);
     const int gy = (g.ny + BY - 3) / (BY - 2);
     const int64_t total = (int64_t)gridDim.x;
     const int64_t Tt = xcd_tile(blockIdx.x, total);
@@ -90,7 +99,7 @@ __global__ __launch_bounds__(BX * BY) void k_sweep(Geom g, Coef cd, SweepPtrs<T>
     const int bz = (int)(Tt / ((int64_t)gx * gy));
 
     const int tx = threadIdx.x, ty = threadIdx.y;
-    const int i = bx * (BX - 2) - 1 + tx;
+    const int i = bx * (W - 2) - 1 + tx;
     const int j = by * (BY - 2) - 1 + ty;
     const int kz0 = bz * g.kz;
     const int kz1 = min(g.nz, kz0 + g.kz);
@@ -100,8 +109,8 @@ __global__ __launch_bounds__(BX * BY) void k_sweep(Geom g, Coef cd, SweepPtrs<T>
     const bool cell = ci && cj;
     const bool vxcol = (i >= 0) && (i <= g.nx) && cj;   // x-faces of this column
     const bool vycol = ci && (j >= 0) && (j <= g.ny);   // y-faces of this column
-    const bool outc = cell && tx >= 1 && tx <= BX - 2 && ty >= 1 && ty <= BY - 2;
-    const bool cellq = cell && tx <= BX - 2 && ty <= BY - 2;
+    const bool outc = cell && tx >= 1 && tx <= W - 2 && ty >= 1 && ty <= BY - 2;
+    const bool cellq = cell && tx <= W - 2 && ty <= BY - 2;
     const bool edge = tx >= 1 && ty >= 1;
 
     // Every load is issued from an address clamped into the padded box
@@ -424,16 +433,17 @@ __global__ __launch_bounds__(BX * BY) void k_sweep(Geom g, Coef cd, SweepPtrs<T>
         cc = cn;
     }
 
-    if (WNORM) {
+    if constexpr (WNORM) {
         // block maximum: wave64 butterfly, then across the waves through LDS
-        __shared__ double red[(BX * BY) / 64][NNORM];
+        static_assert((W * BY) % 64 == 0, "norm variants need whole waves");
+        __shared__ double red[(W * BY) / 64][NNORM];
 #pragma unroll
         for (int q = 0; q < NNORM; ++q) {
             T v = nm[q];
             for (int off = 32; off >= 1; off >>= 1) v = nanmax(v, T(__shfl_xor(v, off, 64)));
             nm[q] = v;
         }
-        const int lin = ty * BX + tx;
+        const int lin = ty * W + tx;
         const int wave = lin >> 6, lane = lin & 63;
         if (lane == 0) {
 #pragma unroll
@@ -442,7 +452,7 @@ __global__ __launch_bounds__(BX * BY) void k_sweep(Geom g, Coef cd, SweepPtrs<T>
         __syncthreads();
         if (lin < NNORM) {
             double v = 0.0;
-            for (int wv = 0; wv < (BX * BY) / 64; ++wv) v = nanmax(v, red[wv][lin]);
+            for (int wv = 0; wv < (W * BY) / 64; ++wv) v = nanmax(v, red[wv][lin]);
             p.partials[(int64_t)blockIdx.x * NNORM + lin] = v;
         }
     }
@@ -479,21 +489,26 @@ __global__ __launch_bounds__(256) void k_reduce_max(const double* __restrict__ p
 
 }  // namespace
 
+template <typename T, int MODE, bool NORMS>
+void launch_sweep(const Geom& g, const Coef& c, const SweepPtrs<T>& p, hipStream_t s) {
+    constexpr int W = sweep_bx<MODE, NORMS>();
+    hipLaunchKernelGGL((k_sweep<T, MODE, NORMS>), dim3((unsigned)iter_grid_blocks(g, W)), dim3(W, BY, 1), 0, s,
+                       g, c, p);
+}
+
 hipError_t launch_iteration(const Geom& g, const Coef& c, const SweepPtrs<double>& p, int mode, int norms,
                             hipStream_t s) {
-    const dim3 block(BX, BY, 1);
-    const dim3 grid((unsigned)iter_grid_blocks(g), 1, 1);
     switch (mode) {
         case MD_THESIS:
-            if (norms) hipLaunchKernelGGL((k_sweep<double, MD_THESIS, true>), grid, block, 0, s, g, c, p);
-            else hipLaunchKernelGGL((k_sweep<double, MD_THESIS, false>), grid, block, 0, s, g, c, p);
+            if (norms) launch_sweep<double, MD_THESIS, true>(g, c, p, s);
+            else launch_sweep<double, MD_THESIS, false>(g, c, p, s);
             break;
         case MD_LINEAR:
-            if (norms) hipLaunchKernelGGL((k_sweep<double, MD_LINEAR, true>), grid, block, 0, s, g, c, p);
-            else hipLaunchKernelGGL((k_sweep<double, MD_LINEAR, false>), grid, block, 0, s, g, c, p);
+            if (norms) launch_sweep<double, MD_LINEAR, true>(g, c, p, s);
+            else launch_sweep<double, MD_LINEAR, false>(g, c, p, s);
             break;
         case MD_RESID:
-            hipLaunchKernelGGL((k_sweep<double, MD_RESID, false>), grid, block, 0, s, g, c, p);
+            launch_sweep<double, MD_RESID, false>(g, c, p, s);
             break;
         default:
             return hipErrorInvalidValue;
@@ -502,19 +517,15 @@ hipError_t launch_iteration(const Geom& g, const Coef& c, const SweepPtrs<double
 }
 
 hipError_t launch_correction(const Geom& g, const Coef& c, const SweepPtrs<float>& p, int norms, hipStream_t s) {
-    const dim3 block(BX, BY, 1);
-    const dim3 grid((unsigned)iter_grid_blocks(g), 1, 1);
-    if (norms) hipLaunchKernelGGL((k_sweep<float, MD_CORR, true>), grid, block, 0, s, g, c, p);
-    else hipLaunchKernelGGL((k_sweep<float, MD_CORR, false>), grid, block, 0, s, g, c, p);
+    if (norms) launch_sweep<float, MD_CORR, true>(g, c, p, s);
+    else launch_sweep<float, MD_CORR, false>(g, c, p, s);
     return hipGetLastError();
 }
 
 hipError_t launch_correction64(const Geom& g, const Coef& c, const SweepPtrs<double>& p, int norms,
                                hipStream_t s) {
-    const dim3 block(BX, BY, 1);
-    const dim3 grid((unsigned)iter_grid_blocks(g), 1, 1);
-    if (norms) hipLaunchKernelGGL((k_sweep<double, MD_CORR, true>), grid, block, 0, s, g, c, p);
-    else hipLaunchKernelGGL((k_sweep<double, MD_CORR, false>), grid, block, 0, s, g, c, p);
+    if (norms) launch_sweep<double, MD_CORR, true>(g, c, p, s);
+    else launch_sweep<double, MD_CORR, false>(g, c, p, s);
     return hipGetLastError();
 }
 

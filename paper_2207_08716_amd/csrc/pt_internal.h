@@ -59,17 +59,26 @@ constexpr int NNORM = 8;
 
 // Tile of the fused sweep: a BX x BY thread block covers a (BX-2) x (BY-2)
 // output tile plus one halo column/row on every side and marches in z.
-constexpr int BX = 64;
+// BX = 66 makes the output tile 64 columns wide: its rows start on 512-byte
+// boundaries of the padded rows (whole cache lines written) and n = 2^k - 1
+// grids fill their last tile; the block is 8 1/4 waves (528 threads).  The
+// variants that also reduce norms use BX_NORMS = 64 (8 whole waves).  Every
+// cell's arithmetic is the same in both tilings.
+constexpr int BX = 66;
+constexpr int BX_NORMS = 64;
 constexpr int BY = 8;
 constexpr int KZ_MAX = 64;
 
-inline int64_t tiles_xy(const Geom& g) {
-    return (int64_t)((g.nx + BX - 3) / (BX - 2)) * ((g.ny + BY - 3) / (BY - 2));
+inline int64_t tiles_xy(const Geom& g, int bx = BX) {
+    return (int64_t)((g.nx + bx - 3) / (bx - 2)) * ((g.ny + BY - 3) / (BY - 2));
 }
 
-inline int64_t iter_grid_blocks(const Geom& g) {
-    return tiles_xy(g) * ((g.nz + g.kz - 1) / g.kz);
+inline int64_t iter_grid_blocks(const Geom& g, int bx = BX) {
+    return tiles_xy(g, bx) * ((g.nz + g.kz - 1) / g.kz);
 }
+
+// Blocks that write per-block norm maxima (size of the partials area).
+inline int64_t norm_blocks(const Geom& g) { return iter_grid_blocks(g, BX_NORMS); }
 
 // Longest z chunk that still gives the 256 CUs a few blocks each (short
 // chunks cost one extra halo plane per chunk).
