@@ -33,12 +33,12 @@ namespace ptk {
 
 namespace {
 
-template <typename T, int W>
+template <typename T, int W, int H>
 struct Lds {
-    T vx[BY][W], vy[BY][W], vz1[BY][W];
-    T pf[BY][W], kc[BY][W], s[BY][W], mu[BY][W], mu1[BY][W];
-    T ptn[BY][W], txx[BY][W], tyy[BY][W], txy[BY][W], w[BY][W];
-    T txz[2][BY][W], tyz[2][BY][W];
+    T vx[H][W], vy[H][W], vz1[H][W];
+    T pf[H][W], kc[H][W], s[H][W], mu[H][W], mu1[H][W];
+    T ptn[H][W], txx[H][W], tyy[H][W], txy[H][W], w[H][W];
+    T txz[2][H][W], tyz[2][H][W];
 };
 
 // Block width of a sweep variant: the plain sweeps use BX (64-column output
@@ -47,6 +47,16 @@ struct Lds {
 template <int MODE, bool NORMS>
 constexpr int sweep_bx() {
     return (NORMS || MODE == MD_RESID) ? BX_NORMS : BX;
+}
+// Block height: taller tiles re-read fewer halo rows but need registers for
+// more waves per CU; the heights below are the tallest that each variant fits
+// without spilling (measured fastest at 511^3).
+template <typename T, int MODE, bool NORMS>
+constexpr int sweep_by() {
+    if (NORMS || MODE == MD_RESID) return BY_NORMS;
+    if (MODE == MD_THESIS) return BY;
+    if (MODE == MD_CORR && sizeof(T) == 4) return BY_CORR32;
+    return BY_LINEAR;
 }
 
 template <typename T>
@@ -80,18 +90,19 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t L, int64_t total) {
 }
 
 template <typename T, int MODE, bool NORMS>
-__global__ __launch_bounds__((sweep_bx<MODE, NORMS>() * BY)) void k_sweep(Geom g, Coef cd, SweepPtrs<T> p) {
+__global__ __launch_bounds__((sweep_bx<MODE, NORMS>() * sweep_by<T, MODE, NORMS>())) void k_sweep(Geom g, Coef cd, SweepPtrs<T> p) {
     constexpr int W = sweep_bx<MODE, NORMS>();
+    constexpr int H = sweep_by<T, MODE, NORMS>();
     constexpr bool UPD_LP = (MODE == MD_THESIS);
     constexpr bool RESID = (MODE == MD_RESID);
     constexpr bool CORR = (MODE == MD_CORR);
     constexpr bool WNORM = NORMS || RESID;
-    __shared__ Lds<T, W> sh;
+    __shared__ Lds<T, W, H> sh;
     const CT<T> c(cd);
     const T zero = T(0), half = T(0.5), one = T(1), two = T(2), quarter = T(0.25);
 
     const int gx = (g.nx + W - 3) / (W - 2);
-    const int gy = (g.ny + BY - 3) / (BY - 2);
+    const int gy = (g.ny + H - 3) / (H - 2);
     const int64_t total = (int64_t)gridDim.x;
     const int64_t Tt = xcd_tile(blockIdx.x, total);
     const int bx = (int)(Tt % gx);
@@ -100,7 +111,7 @@ __global__ __launch_bounds__((sweep_bx<MODE, NORMS>() * BY)) void k_sweep(Geom g
 
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int i = bx * (W - 2) - 1 + tx;
-    const int j = by * (BY - 2) - 1 + ty;
+    const int j = by * (H - 2) - 1 + ty;
     const int kz0 = bz * g.kz;
     const int kz1 = min(g.nz, kz0 + g.kz);
 
@@ -109,8 +120,8 @@ __global__ __launch_bounds__((sweep_bx<MODE, NORMS>() * BY)) void k_sweep(Geom g
     const bool cell = ci && cj;
     const bool vxcol = (i >= 0) && (i <= g.nx) && cj;   // x-faces of this column
     const bool vycol = ci && (j >= 0) && (j <= g.ny);   // y-faces of this column
-    const bool outc = cell && tx >= 1 && tx <= W - 2 && ty >= 1 && ty <= BY - 2;
-    const bool cellq = cell && tx <= W - 2 && ty <= BY - 2;
+    const bool outc = cell && tx >= 1 && tx <= W - 2 && ty >= 1 && ty <= H - 2;
+    const bool cellq = cell && tx <= W - 2 && ty <= H - 2;
     const bool edge = tx >= 1 && ty >= 1;
 
     // Every load is issued from an address clamped into the padded box
@@ -435,8 +446,8 @@ __global__ __launch_bounds__((sweep_bx<MODE, NORMS>() * BY)) void k_sweep(Geom g
 
     if constexpr (WNORM) {
         // block maximum: wave64 butterfly, then across the waves through LDS
-        static_assert((W * BY) % 64 == 0, "norm variants need whole waves");
-        __shared__ double red[(W * BY) / 64][NNORM];
+        static_assert((W * H) % 64 == 0, "norm variants need whole waves");
+        __shared__ double red[(W * H) / 64][NNORM];
 #pragma unroll
         for (int q = 0; q < NNORM; ++q) {
             T v = nm[q];
@@ -452,7 +463,7 @@ __global__ __launch_bounds__((sweep_bx<MODE, NORMS>() * BY)) void k_sweep(Geom g
         __syncthreads();
         if (lin < NNORM) {
             double v = 0.0;
-            for (int wv = 0; wv < (W * BY) / 64; ++wv) v = nanmax(v, red[wv][lin]);
+            for (int wv = 0; wv < (W * H) / 64; ++wv) v = nanmax(v, red[wv][lin]);
             p.partials[(int64_t)blockIdx.x * NNORM + lin] = v;
         }
     }
@@ -491,8 +502,8 @@ __global__ __launch_bounds__(256) void k_reduce_max(const double* __restrict__ p
 
 template <typename T, int MODE, bool NORMS>
 void launch_sweep(const Geom& g, const Coef& c, const SweepPtrs<T>& p, hipStream_t s) {
-    constexpr int W = sweep_bx<MODE, NORMS>();
-    hipLaunchKernelGGL((k_sweep<T, MODE, NORMS>), dim3((unsigned)iter_grid_blocks(g, W)), dim3(W, BY, 1), 0, s,
+    constexpr int W = sweep_bx<MODE, NORMS>(), H = sweep_by<T, MODE, NORMS>();
+    hipLaunchKernelGGL((k_sweep<T, MODE, NORMS>), dim3((unsigned)iter_grid_blocks(g, W, H)), dim3(W, H, 1), 0, s,
                        g, c, p);
 }
 

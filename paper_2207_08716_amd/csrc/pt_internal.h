@@ -65,20 +65,23 @@ constexpr int NNORM = 8;
 // variants that also reduce norms use BX_NORMS = 64 (8 whole waves).  Every
 // cell's arithmetic is the same in both tilings.
 constexpr int BX = 66;
+constexpr int BY = 8;          // thesis sweep
+constexpr int BY_LINEAR = 10;  // linear and FP64 correction sweeps
+constexpr int BY_CORR32 = 12;  // FP32 correction sweep
 constexpr int BX_NORMS = 64;
-constexpr int BY = 8;
+constexpr int BY_NORMS = 8;
 constexpr int KZ_MAX = 64;
 
-inline int64_t tiles_xy(const Geom& g, int bx = BX) {
-    return (int64_t)((g.nx + bx - 3) / (bx - 2)) * ((g.ny + BY - 3) / (BY - 2));
+inline int64_t tiles_xy(const Geom& g, int bx = BX, int by = BY) {
+    return (int64_t)((g.nx + bx - 3) / (bx - 2)) * ((g.ny + by - 3) / (by - 2));
 }
 
-inline int64_t iter_grid_blocks(const Geom& g, int bx = BX) {
-    return tiles_xy(g, bx) * ((g.nz + g.kz - 1) / g.kz);
+inline int64_t iter_grid_blocks(const Geom& g, int bx = BX, int by = BY) {
+    return tiles_xy(g, bx, by) * ((g.nz + g.kz - 1) / g.kz);
 }
 
 // Blocks that write per-block norm maxima (size of the partials area).
-inline int64_t norm_blocks(const Geom& g) { return iter_grid_blocks(g, BX_NORMS); }
+inline int64_t norm_blocks(const Geom& g) { return iter_grid_blocks(g, BX_NORMS, BY_NORMS); }
 
 // Longest z chunk that still gives the 256 CUs a few blocks each (short
 // chunks cost one extra halo plane per chunk).
