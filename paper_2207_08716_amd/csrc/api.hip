@@ -25,6 +25,7 @@ struct pt_grid {
     float* mws = nullptr;      // FP32 workspace of the mixed-precision solve
     size_t mws_bytes = 0;
     bool mws_clean = false;    // both correction copies zeroed once
+    int mx_copy = 0;           // correction copy holding the present R_d
     hipStream_t stream = nullptr;
     int64_t iter = 0;          // iteration count within the current step
     double ref_v = 0.0, ref_p = 0.0;   // residual reference of the step (g_V0, g_P0)
@@ -505,6 +506,7 @@ pt_status pt_bind_mixed_workspace(pt_grid* g, void* dev_ptr, size_t bytes) {
     g->mws = static_cast<float*>(dev_ptr);
     g->mws_bytes = bytes;
     g->mws_clean = false;
+    g->mx_copy = 0;
     return PT_OK;
 }
 
@@ -604,10 +606,13 @@ pt_status pt_solve_mixed(pt_grid* g, double rtol, double eta_in, int64_t max_inn
         r = group_rho(nm, g->ref_v, g->ref_p);
         if (r <= rtol || outer >= max_outer) break;
         const double gv = nm.f, gp = std::fmax(nm.rpt, nm.rpf);
-        // correction d = 0, damped residual 0 (copy 0 holds the present d)
-        e = hipMemsetAsync(mx(g, 0), 0, 8 * box_bytes, g->stream);
+        // correction d = 0; the damped residual R_d carries over from the
+        // previous correction: with it, the PT iteration on A d = -r(x) is
+        // the continuation of the PT iteration on x itself (same operator,
+        // same pseudo-steps), so a restart costs no convergence
+        int cp = g->mx_copy;
+        e = hipMemsetAsync(mx(g, cp ? 8 : 0), 0, 5 * box_bytes, g->stream);
         if (e != hipSuccess) return hip_fail(g, e, "correction clear");
-        int cp = 0;
         double best = INFINITY;
         int since_best = 0;
         for (int64_t m = 1; m <= max_inner; ++m) {
@@ -632,6 +637,7 @@ pt_status pt_solve_mixed(pt_grid* g, double rtol, double eta_in, int64_t max_inn
         }
         e = launch_apply_correction(g->geom, mixed_ptrs(g, cp), g->stream);
         if (e != hipSuccess) return hip_fail(g, e, "apply correction");
+        g->mx_copy = cp;
         ++outer;
     }
     if (inner_iters) *inner_iters = inner_total;
