@@ -150,14 +150,16 @@ pt_status pt_bind_workspace(pt_grid* g, void* dev_ptr, size_t bytes);
 /* Stream for all launches (a hipStream_t; NULL = the null stream). */
 pt_status pt_set_stream(pt_grid* g, void* hip_stream);
 
-/* Progress report of long calls (pt_adjoint_run): fn(user, phase, step,
- * stage, sweeps) is called on the calling thread after every stage, with
- * phase PT_PROGRESS_FORWARD (recorded forward), PT_PROGRESS_RECOMPUTE
- * (a checkpointed step recomputed) or PT_PROGRESS_REVERSE (a transposed
- * stage solve), and the stage's sweep count.  fn = NULL: no reports. */
+/* Progress report of long calls (pt_picard_step, pt_adjoint_run):
+ * fn(user, phase, step, stage, sweeps) is called on the calling thread after
+ * every stage, with phase PT_PROGRESS_STAGE (a stage of pt_picard_step),
+ * PT_PROGRESS_FORWARD (recorded forward), PT_PROGRESS_RECOMPUTE (a
+ * checkpointed step recomputed) or PT_PROGRESS_REVERSE (a transposed stage
+ * solve), and the stage's sweep count.  fn = NULL: no reports. */
 #define PT_PROGRESS_FORWARD 0
 #define PT_PROGRESS_REVERSE 1
 #define PT_PROGRESS_RECOMPUTE 2
+#define PT_PROGRESS_STAGE 3
 typedef void (*pt_progress_fn)(void* user, int32_t phase, int32_t step, int32_t stage, int64_t sweeps);
 pt_status pt_set_progress(pt_grid* g, pt_progress_fn fn, void* user);
 pt_status pt_set_params(pt_grid* g, const pt_params* params);
@@ -215,6 +217,19 @@ pt_status pt_set_residual_reference(pt_grid* g, double gv, double gp);
  * fraction. */
 pt_status pt_porosity_step(pt_grid* g);
 
+/* One physical step of the Picard schedule (the thesis's M-P driver): the
+ * step set-up of pt_begin_step(update_history), then n_picard stages of
+ * { refresh without relaxation (eqs (23)-(26)); linear solve of the frozen
+ * system to the relative residual rtol (pt_solve_linear; or, with mixed,
+ * pt_solve_mixed with inner tolerance eta_in and at most 64 corrections,
+ * max_iter sweeps per correction); porosity step of eq (22) }.  sweeps: PT
+ * sweeps of all stages (FP64 or FP32); rho: the largest final relative
+ * residual.  Synchronises.  PT_ENOTCONV: a stage missed rtol within its
+ * limits; the step stops there with a valid state.  The mixed form needs the
+ * mixed workspace. */
+pt_status pt_picard_step(pt_grid* g, int32_t update_history, int32_t n_picard, double rtol, int64_t max_iter,
+                         int32_t mixed, double eta_in, int64_t* sweeps, double* rho);
+
 /* ---- Mixed precision (FP32 sweeps inside FP64 defect correction) --------
  * FP32 workspace for the correction system: query the size (24 FP32 padded
  * boxes), then bind a device buffer (256-byte aligned) of at least that many
@@ -231,7 +246,8 @@ pt_status pt_residual(pt_grid* g);
 /* One linear Picard stage solved by defect correction (coefficients and
  * porosity frozen, as pt_solve_linear): repeat { r = residual of x in FP64;
  * stop when rho (as in pt_solve_linear, same step reference) <= rtol; solve
- * A d = -r by FP32 PT sweeps from d = 0 until the correction residual falls
+ * A d = -r by FP32 PT sweeps from d = 0 (the damped residual of d carried
+ * over from the previous correction) until the correction residual falls
  * to eta_in times r, stops improving (no new 1 % minimum in 40 checks: the
  * FP32 round-off floor) or max_inner sweeps, checked every nup sweeps;
  * x += d in FP64 }.  At most max_outer corrections.  Synchronises.

@@ -45,12 +45,12 @@ EXPORTS = ["pt_create", "pt_destroy", "pt_field_elems", "pt_bind_field", "pt_wor
            "pt_bind_workspace", "pt_set_stream", "pt_set_progress", "pt_set_params", "pt_current", "pt_begin_step",
            "pt_refresh", "pt_iteration", "pt_iterate", "pt_last_norms", "pt_solve_linear",
            "pt_residual_reference", "pt_set_residual_reference",
-           "pt_porosity_step", "pt_mixed_workspace_size", "pt_bind_mixed_workspace", "pt_residual",
+           "pt_porosity_step", "pt_picard_step", "pt_mixed_workspace_size", "pt_bind_mixed_workspace", "pt_residual",
            "pt_solve_mixed", "pt_adjoint_workspace_size", "pt_bind_adjoint_workspace", "pt_set_log_k0",
            "pt_misfit", "pt_adjoint_stage", "pt_adjoint_tape_size", "pt_adjoint_run", "pt_copy", "pt_status_str", "pt_last_error", "pt_abi_version"]
 
 PROGRESS_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int64)
-PROGRESS_PHASE = {0: "forward", 1: "reverse", 2: "recompute"}
+PROGRESS_PHASE = {0: "forward", 1: "reverse", 2: "recompute", 3: "stage"}
 
 _lib = None
 
@@ -89,6 +89,8 @@ def load(path: str = LIB_PATH):
     lib.pt_last_norms.argtypes = [vp, P(Norms)]
     lib.pt_solve_linear.argtypes = [vp, C.c_double, C.c_int64, P(C.c_int64), P(C.c_double)]
     lib.pt_porosity_step.argtypes = [vp]
+    lib.pt_picard_step.argtypes = [vp, C.c_int32, C.c_int32, C.c_double, C.c_int64, C.c_int32, C.c_double,
+                                   P(C.c_int64), P(C.c_double)]
     lib.pt_residual_reference.argtypes = [vp, P(C.c_double), P(C.c_double)]
     lib.pt_set_residual_reference.argtypes = [vp, C.c_double, C.c_double]
     lib.pt_copy.argtypes = [vp, vp, vp, C.c_int64]

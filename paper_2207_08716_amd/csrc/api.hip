@@ -559,6 +559,9 @@ MixedPtrs mixed_ptrs(pt_grid* g, int cp) {
     return m;
 }
 
+// Corrections per stage of a mixed Picard step (each gains about 1e-3).
+constexpr int32_t PICARD_MAX_CORRECTIONS = 64;
+
 double group_rho(const pt_norms& nm, double g0v, double g0p) {
     double r = 0.0;
     if (g0v > 0.0) r = std::fmax(r, nm.f / g0v);
@@ -767,6 +770,37 @@ pt_status transposed_solve(pt_grid* g, const double* kc, const double* mus, doub
     return (r <= rtol) ? PT_OK : PT_ENOTCONV;
 }
 }  // namespace
+
+pt_status pt_picard_step(pt_grid* g, int32_t update_history, int32_t n_picard, double rtol, int64_t max_iter,
+                         int32_t mixed, double eta_in, int64_t* sweeps, double* rho) {
+    if (!g || n_picard < 1 || !(rtol > 0.0) || max_iter < 1) return PT_EINVAL;
+    if (mixed && !(eta_in > 0.0 && eta_in < 1.0)) return PT_EINVAL;
+    pt_status st = pt_begin_step(g, update_history ? 1 : 0);
+    if (st != PT_OK) return st;
+    int64_t total = 0;
+    double rmax = 0.0;
+    for (int p = 0; p < n_picard; ++p) {
+        st = pt_refresh(g, 1.0, 1.0);
+        if (st != PT_OK) return st;
+        int64_t it = 0;
+        double r = 0.0;
+        if (mixed) {
+            int32_t outer = 0;
+            st = pt_solve_mixed(g, rtol, eta_in, max_iter, PICARD_MAX_CORRECTIONS, &it, &outer, &r);
+        } else {
+            st = pt_solve_linear(g, rtol, max_iter, &it, &r);
+        }
+        total += it;
+        rmax = std::fmax(rmax, r);
+        if (sweeps) *sweeps = total;
+        if (rho) *rho = rmax;
+        if (st != PT_OK) return st;   // PT_ENOTCONV: the step stops at this stage
+        st = pt_porosity_step(g);
+        if (st != PT_OK) return st;
+        if (g->progress) g->progress(g->progress_user, PT_PROGRESS_STAGE, 0, p, it);
+    }
+    return PT_OK;
+}
 
 pt_status pt_adjoint_workspace_size(const pt_grid* g, int32_t max_sensors, size_t* bytes) {
     if (!g || !bytes || max_sensors < 1) return PT_EINVAL;

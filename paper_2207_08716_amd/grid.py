@@ -181,6 +181,19 @@ class Grid:
     def porosity_step(self):
         _check(self.lib, self.h, self.lib.pt_porosity_step(self.h), "porosity_step")
 
+    def picard_step(self, update_history, n_picard, rtol, max_iter=2_000_000, mixed=False, eta_in=1e-4):
+        """One physical step of the Picard schedule (see pt_picard_step):
+        returns (sweeps, rho, converged)."""
+        if mixed:
+            self.enable_mixed()
+        sweeps = C.c_int64()
+        rho = C.c_double()
+        st = _check(self.lib, self.h, self.lib.pt_picard_step(self.h, int(bool(update_history)), int(n_picard),
+                                                               float(rtol), int(max_iter), int(bool(mixed)),
+                                                               float(eta_in), C.byref(sweeps), C.byref(rho)),
+                    "picard_step")
+        return sweeps.value, rho.value, st == 0
+
     # ---- mixed precision ----------------------------------------------------
     def enable_mixed(self):
         """Allocate and bind the FP32 workspace of the defect-correction solve."""

@@ -19,18 +19,9 @@ def thesis_step(g: Grid, n_iter: int, step_index: int):
     g.iterate(n_iter)
 
 
-def picard_step(g: Grid, n_picard: int, rtol: float, step_index: int, max_iter=1_000_000):
-    """One physical step of the Picard schedule: per stage, a refresh without
-    relaxation, a linear PT solve to rtol, then the porosity time step."""
-    g.begin_step(update_history=step_index >= 1)
-    out = []
-    for _ in range(n_picard):
-        g.refresh(1.0, 1.0)
-        it, rho, ok = g.solve_linear(rtol, max_iter)
-        out.append((it, rho, ok))
-        g.porosity_step()
-    return out
-
-
-def phi(g: Grid) -> np.ndarray:
-    return 1.0 - np.exp(g.get("lp"))
+def picard_step(g: Grid, n_picard: int, rtol: float, step_index: int, max_iter=1_000_000, mixed=False,
+                eta_in=1e-4):
+    """One physical step of the Picard schedule (pt_picard_step): per stage, a
+    refresh without relaxation, a linear solve to rtol (FP64 PT sweeps, or
+    FP32 sweeps inside FP64 defect correction), then the porosity time step."""
+    return g.picard_step(step_index >= 1, n_picard, rtol, max_iter, mixed, eta_in)

@@ -78,11 +78,9 @@ def test_mixed_picard_step_matches_oracle():
     cfg = inputs.config_mixed(n)
     f = inputs.initial_fields(cfg)
     g = _grid(cfg, f)
-    g.begin_step(False)
-    for _ in range(2):
-        g.refresh(1.0, 1.0)
-        g.solve_mixed(1e-10, 1e-4)
-        g.porosity_step()
+    sweeps, rho, ok = g.picard_step(False, 2, 1e-10, mixed=True, eta_in=1e-4)   # pt_picard_step
+    print("mixed Picard step", sweeps, rho, ok)
+    assert ok
     o = oracle.Oracle(cfg.phys, n, n, n, f["phi"], f["k0"])
     counts = o.picard_step(2, 1e-10, 200000)
     print(counts)
