@@ -175,7 +175,7 @@ def fp32_sweep_time(g, k_lo=45, k_hi=165):
     return (ts[1] - ts[0]) / (k_hi - k_lo)
 
 
-def adjoint_measure(n, n_steps=10, n_picard=5, rtol=1e-10, ns=64, checkpoint=False):
+def adjoint_measure(n, n_steps=10, n_picard=5, rtol=1e-10, ns=64, checkpoint=False, mixed=False):
     """Wall time of the recorded Picard run and its adjoint (pt_adjoint_run)
     on the adjoint workload at n^3: n_steps steps of n_picard stages, forward
     and transposed solves to rtol, ns sensors, observations d = 0."""
@@ -198,11 +198,12 @@ def adjoint_measure(n, n_steps=10, n_picard=5, rtol=1e-10, ns=64, checkpoint=Fal
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     J, grad, fit, ait = g.adjoint_run(sensors, np.zeros(ns), n_steps, n_picard, rtol, rtol,
-                                      checkpoint=checkpoint)
+                                      checkpoint=checkpoint, mixed=mixed)
     t1 = time.perf_counter()
     t_fwd = max(t for ph, t in marks if ph == "forward") - t0
     out = {"n": n, "steps": n_steps, "picard_stages": n_picard, "rtol": rtol, "sensors": ns,
-           "checkpoint": bool(checkpoint), "J": J, "max_abs_grad": float(grad.abs().max()),
+           "checkpoint": bool(checkpoint), "mixed": bool(mixed), "J": J,
+           "max_abs_grad": float(grad.abs().max()),
            "forward_s": round(t_fwd, 3), "reverse_s": round(t1 - t0 - t_fwd, 3),
            "forward_sweeps": fit, "transposed_sweeps": ait,
            "tape_gb": round(g.tape_bytes / 1e9, 3),
@@ -234,6 +235,8 @@ def main(argv=None):
     ap.add_argument("--adjoint-stages", type=int, default=5, help="Picard stages per step of the adjoint run")
     ap.add_argument("--adjoint-checkpoint", action="store_true",
                     help="run the adjoint measurement with step checkpoints")
+    ap.add_argument("--adjoint-mixed", action="store_true",
+                    help="run the adjoint measurement with FP32 sweeps inside FP64 defect correction")
     args = ap.parse_args(argv)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -353,7 +356,7 @@ def main(argv=None):
     out["time_to_tol"] = time_to_tol(args.ttt_n) if args.ttt_n > 0 else None
     if args.adjoint_n > 0:
         out["adjoint_run"] = adjoint_measure(args.adjoint_n, args.adjoint_steps, args.adjoint_stages,
-                                             checkpoint=args.adjoint_checkpoint)
+                                             checkpoint=args.adjoint_checkpoint, mixed=args.adjoint_mixed)
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(cfg, fields, args.cpu_iters)

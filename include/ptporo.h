@@ -299,21 +299,29 @@ pt_status pt_adjoint_stage(pt_grid* g, const int64_t* sensors, int32_t ns, const
  * constant (no derivative).  Needs PT_F_K0FIELD and the Newtonian law (no
  * PT_F_POWERLAW, PT_F_DPCAP, PT_F_MECHOFF), and the adjoint workspace.
  *
+ * options: PT_ADJ_CHECKPOINT (tape below) and PT_ADJ_MIXED: the forward
+ * stages by pt_solve_mixed and the transposed solves by defect correction
+ * too (FP32 sweeps; the FP64 residual of the transposed system is the stage
+ * residual with gravity off and the right-hand side put in the history and
+ * old-pressure terms; inner tolerance 1e-4, at most 64 corrections per
+ * solve; needs the mixed workspace and beta_d > 0).
  * The tape is a caller-owned device buffer, 256-byte aligned, of at least
- * pt_adjoint_tape_size bytes.  checkpoint = 0: it receives every stage's V,
+ * pt_adjoint_tape_size(options) bytes.  Without PT_ADJ_CHECKPOINT it receives every stage's V,
  * Pt, Pf, incoming ln(1-phi), k/mu_f and eta_phi (8 padded boxes per stage;
- * n_steps * n_picard * 8 boxes).  checkpoint = 1: it keeps each step's start
+ * n_steps * n_picard * 8 boxes).  With PT_ADJ_CHECKPOINT it keeps each step's start
  * state (V, Pt, Pf, ln(1-phi), R, stress history: 15 boxes per step) plus
  * one step's stages (n_picard * 8 boxes); the reverse sweep recomputes each
  * step from its checkpoint, bitwise the recorded run, at the cost of a
  * second forward pass.  grad_dev: one FP64 padded box, overwritten (cells).
- * On return the grid holds the end state of the run (checkpoint = 0) or of
- * its first step (checkpoint = 1).  Synchronises.  PT_ENOTCONV if a forward
+ * On return the grid holds the end state of the run (without
+ * PT_ADJ_CHECKPOINT) or of its first step (with it).  Synchronises.  PT_ENOTCONV if a forward
  * or transposed solve misses its tolerance within max_iter (nothing after
  * it is computed). */
-pt_status pt_adjoint_tape_size(const pt_grid* g, int32_t n_steps, int32_t n_picard, int32_t checkpoint,
+#define PT_ADJ_CHECKPOINT 1
+#define PT_ADJ_MIXED 2
+pt_status pt_adjoint_tape_size(const pt_grid* g, int32_t n_steps, int32_t n_picard, int32_t options,
                                size_t* bytes);
-pt_status pt_adjoint_run(pt_grid* g, int32_t n_steps, int32_t n_picard, int32_t checkpoint, double rtol,
+pt_status pt_adjoint_run(pt_grid* g, int32_t n_steps, int32_t n_picard, int32_t options, double rtol,
                          double adj_rtol, int64_t max_iter, const int64_t* sensors, int32_t ns, const double* d_obs,
                          void* tape, size_t tape_bytes, void* grad_dev, double* J, int64_t* fwd_iters,
                          int64_t* adj_iters);

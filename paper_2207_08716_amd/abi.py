@@ -16,6 +16,7 @@ FIELD_ID = {n: i for i, n in enumerate(FIELDS)}
 NPING = 9
 
 F_POWERLAW, F_DPCAP, F_K0FIELD, F_MECHOFF = 1, 2, 4, 8
+ADJ_CHECKPOINT, ADJ_MIXED = 1, 2
 
 STATUS = {0: "PT_OK", 1: "PT_ENOTCONV", -1: "PT_EINVAL", -2: "PT_EDEVICE",
           -3: "PT_EDIVERGED", -4: "PT_EDOMAIN", -5: "PT_ESTATE"}

@@ -296,6 +296,25 @@ __global__ __launch_bounds__(AB) void k_adj_scale(Geom g, Coef c, AdjPtrs a) {
     }
 }
 
+// Old pressures that make the stage residual at zero equal the transposed
+// solve's right-hand side (rhs slots hold -xbar): with gravity off and the
+// history term set to -xbar_V, F(0) = (-xbar_V, beta_d/dt (-Pto + alpha Pfo),
+// beta_d/dt (alpha Pto - (alpha/B) Pfo)) = -xbar, so that F(lambda) =
+// J_F lambda - xbar and a defect-correction solve of F = 0 is the transposed
+// solve.
+__global__ __launch_bounds__(AB) void k_adj_oldvalues(Geom g, Coef c, const double* __restrict__ rpt,
+                                                      const double* __restrict__ rpf, double* __restrict__ pto,
+                                                      double* __restrict__ pfo) {
+    Idx q;
+    if (!box_index(g, (int64_t)blockIdx.x * AB + threadIdx.x, q)) return;
+    if (q.i >= g.nx || q.j >= g.ny || q.k >= g.nz) return;
+    const int64_t o = at(g, q.i, q.j, q.k);
+    const double xt = -rpt[o], xf = -rpf[o];
+    const double f = (xf + c.alpha * xt) * c.dt / (c.beta_d * (c.ab - c.alpha * c.alpha));
+    pfo[o] = f;
+    pto[o] = c.alpha * f + xt * c.dt / c.beta_d;
+}
+
 // Largest |value| over five padded boxes (the transposed solve's right-hand
 // side): per-block maxima into slot 0 of the norm partials, other slots 0.
 struct Five {
@@ -346,6 +365,12 @@ hipError_t launch_adj_step(const Geom& g, const Coef& c, const AdjPtrs& a, hipSt
 hipError_t launch_adj_history(const Geom& g, const Coef& c, const AdjPtrs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_adj_history, grid_of(g), dim3(AB), 0, s, g, c, a);
     hipLaunchKernelGGL(k_adj_scale, grid_of(g), dim3(AB), 0, s, g, c, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_oldvalues(const Geom& g, const Coef& c, const double* rpt, const double* rpf, double* pto,
+                                double* pfo, hipStream_t s) {
+    hipLaunchKernelGGL(k_adj_oldvalues, grid_of(g), dim3(AB), 0, s, g, c, rpt, rpf, pto, pfo);
     return hipGetLastError();
 }
 

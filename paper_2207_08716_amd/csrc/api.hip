@@ -571,23 +571,38 @@ double group_rho(const pt_norms& nm, double g0v, double g0p) {
 
 }  // namespace
 
-pt_status pt_solve_mixed(pt_grid* g, double rtol, double eta_in, int64_t max_inner, int32_t max_outer,
-                         int64_t* inner_iters, int32_t* outer_iters, double* rho) {
-    if (!g || !(rtol > 0.0) || !(eta_in > 0.0 && eta_in < 1.0) || max_inner < 1 || max_outer < 1)
-        return PT_EINVAL;
-    pt_status st = check_ready(g);
-    if (st != PT_OK) return st;
-    if (!g->mws) return fail(g, PT_EINVAL, "mixed workspace not bound");
-    if (g->prm.flags & PT_F_MECHOFF) return fail(g, PT_EINVAL, "mixed precision does not support PT_F_MECHOFF");
+}  // extern "C"
+
+namespace {
+
+// What a defect-correction solve works on: the FP64 residual sweep's inputs
+// (x, coefficients, old values or right-hand side), the FP64 fields the
+// correction is added to, and the residual's constants.
+struct MixedTarget {
+    SweepPtrs<double> resid;
+    MixedPtrs m;
+    Coef coef;
+};
+
+// Defect correction: repeat { r = FP64 residual of x; stop when rho <= rtol
+// (reference: ref_v/ref_p, set from the first residual if !ref_set); FP32
+// PT sweeps on A d = -r from d = 0, the damped residual of d carried over in
+// correction copy `copy`; x += d }.
+pt_status mixed_core(pt_grid* g, const MixedTarget& t, double rtol, double eta_in, int64_t max_inner,
+                     int32_t max_outer, double& ref_v, double& ref_p, bool& ref_set, int& copy,
+                     int64_t* inner_iters, int32_t* outer_iters, double* rho) {
     const int64_t box_bytes = mx_box(g) * (int64_t)sizeof(float);
-    hipError_t e;
-    if (!g->mws_clean) {
-        e = hipMemsetAsync(g->mws, 0, 16 * box_bytes, g->stream);
-        if (e != hipSuccess) return hip_fail(g, e, "mixed workspace clear");
-        g->mws_clean = true;
-    }
-    e = launch_prepare_mixed(g->geom, mixed_ptrs(g, 0), g->stream);
+    MixedPtrs m = t.m;
+    m.kc32 = mx(g, 21); m.mus32 = mx(g, 22); m.chi32 = mx(g, 23);
+    hipError_t e = launch_prepare_mixed(g->geom, m, g->stream);
     if (e != hipSuccess) return hip_fail(g, e, "prepare mixed");
+    SweepPtrs<double> rp = t.resid;
+    rp.res_fx = mx(g, MX_RES + 0);
+    rp.res_fy = mx(g, MX_RES + 1);
+    rp.res_fz = mx(g, MX_RES + 2);
+    rp.res_rpt = mx(g, MX_RES + 3);
+    rp.res_rpf = mx(g, MX_RES + 4);
+    rp.partials = static_cast<double*>(g->ws);
     const int64_t nup = g->prm.nup;
     // the inner solve stops when its residual has not reached a new minimum
     // (by 1 %) for this many checks: FP32 cannot go below its round-off level
@@ -595,31 +610,34 @@ pt_status pt_solve_mixed(pt_grid* g, double rtol, double eta_in, int64_t max_inn
     double r = INFINITY;
     int64_t inner_total = 0;
     int32_t outer = 0;
+    pt_status st;
     for (;;) {
-        st = pt_residual(g);
+        e = launch_iteration(g->geom, t.coef, rp, MD_RESID, 1, g->stream);
+        if (e != hipSuccess) return hip_fail(g, e, "residual");
+        st = reduce_norms(g);
         if (st != PT_OK) return st;
         pt_norms nm;
         st = read_norms(g, &nm);
         if (st != PT_OK) return st;
-        if (!g->ref_set) {
-            g->ref_v = nm.f;
-            g->ref_p = std::fmax(nm.rpt, nm.rpf);
-            g->ref_set = true;
+        if (!ref_set) {
+            ref_v = nm.f;
+            ref_p = std::fmax(nm.rpt, nm.rpf);
+            ref_set = true;
         }
-        r = group_rho(nm, g->ref_v, g->ref_p);
+        r = group_rho(nm, ref_v, ref_p);
         if (r <= rtol || outer >= max_outer) break;
         const double gv = nm.f, gp = std::fmax(nm.rpt, nm.rpf);
         // correction d = 0; the damped residual R_d carries over from the
         // previous correction: with it, the PT iteration on A d = -r(x) is
         // the continuation of the PT iteration on x itself (same operator,
         // same pseudo-steps), so a restart costs no convergence
-        int cp = g->mx_copy;
+        int cp = copy;
         e = hipMemsetAsync(mx(g, cp ? 8 : 0), 0, 5 * box_bytes, g->stream);
         if (e != hipSuccess) return hip_fail(g, e, "correction clear");
         double best = INFINITY;
         int since_best = 0;
-        for (int64_t m = 1; m <= max_inner; ++m) {
-            const bool chk = (m % nup == 0);
+        for (int64_t it = 1; it <= max_inner; ++it) {
+            const bool chk = (it % nup == 0);
             st = correction_sweep(g, cp, chk ? 1 : 0);
             if (st != PT_OK) return st;
             cp ^= 1;
@@ -638,15 +656,51 @@ pt_status pt_solve_mixed(pt_grid* g, double rtol, double eta_in, int64_t max_inn
                 }
             }
         }
-        e = launch_apply_correction(g->geom, mixed_ptrs(g, cp), g->stream);
+        const int b = cp ? 8 : 0;
+        m.dvx = mx(g, b + 0); m.dvy = mx(g, b + 1); m.dvz = mx(g, b + 2);
+        m.dpt = mx(g, b + 3); m.dpf = mx(g, b + 4);
+        e = launch_apply_correction(g->geom, m, g->stream);
         if (e != hipSuccess) return hip_fail(g, e, "apply correction");
-        g->mx_copy = cp;
+        copy = cp;
         ++outer;
     }
-    if (inner_iters) *inner_iters = inner_total;
-    if (outer_iters) *outer_iters = outer;
+    if (inner_iters) *inner_iters += inner_total;
+    if (outer_iters) *outer_iters += outer;
     if (rho) *rho = r;
     return (r <= rtol) ? PT_OK : PT_ENOTCONV;
+}
+
+pt_status mixed_ready(pt_grid* g) {
+    if (!g->mws) return fail(g, PT_EINVAL, "mixed workspace not bound");
+    if (g->prm.flags & PT_F_MECHOFF) return fail(g, PT_EINVAL, "mixed precision does not support PT_F_MECHOFF");
+    if (!g->mws_clean) {
+        hipError_t e = hipMemsetAsync(g->mws, 0, 16 * mx_box(g) * (int64_t)sizeof(float), g->stream);
+        if (e != hipSuccess) return hip_fail(g, e, "mixed workspace clear");
+        g->mws_clean = true;
+    }
+    return PT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pt_status pt_solve_mixed(pt_grid* g, double rtol, double eta_in, int64_t max_inner, int32_t max_outer,
+                         int64_t* inner_iters, int32_t* outer_iters, double* rho) {
+    if (!g || !(rtol > 0.0) || !(eta_in > 0.0 && eta_in < 1.0) || max_inner < 1 || max_outer < 1)
+        return PT_EINVAL;
+    pt_status st = check_ready(g);
+    if (st != PT_OK) return st;
+    st = mixed_ready(g);
+    if (st != PT_OK) return st;
+    MixedTarget t;
+    t.resid = sweep_ptrs(g);
+    t.m = mixed_ptrs(g, 0);
+    t.coef = g->coef;
+    if (inner_iters) *inner_iters = 0;
+    if (outer_iters) *outer_iters = 0;
+    return mixed_core(g, t, rtol, eta_in, max_inner, max_outer, g->ref_v, g->ref_p, g->ref_set, g->mx_copy,
+                      inner_iters, outer_iters, rho);
 }
 
 // ---- adjoint of a linear Picard stage ---------------------------------------
@@ -655,10 +709,11 @@ namespace {
 // [16..20] right-hand side (f, r_Pt, r_Pf), [21] chi; for the run adjoint
 // [22], [23] L_bar in/out, [24] eta_bar, [25] s_bar, [26..28] Pto/Pfo/Lo
 // adjoints, [29..31] history-term adjoint, [32..37] So adjoint (xx yy zz xy xz
-// yz); then the sensor tail: offsets (int64), gathered values, seeds.
-constexpr int AD_NBOX = 38;
+// yz), [38..39] old pressures of a mixed transposed solve; then the sensor
+// tail: offsets (int64), gathered values, seeds.
+constexpr int AD_NBOX = 40;
 constexpr int AD_RHS = 16, AD_CHI = 21, AD_LBAR = 22, AD_ETAB = 24, AD_SB = 25, AD_OLD = 26, AD_FB = 29,
-              AD_SO = 32;
+              AD_SO = 32, AD_MXOLD = 38;
 // per recorded stage: V (3), Pt, Pf, incoming ln(1-phi), k/mu_f, eta_phi
 constexpr int TAPE_NBOX = 8;
 size_t ad_needed(const pt_grid* g, int32_t max_sensors) {
@@ -768,6 +823,43 @@ pt_status transposed_solve(pt_grid* g, const double* kc, const double* mus, doub
     if (iters) *iters += it;
     if (rho) *rho = std::fmax(*rho, r);
     return (r <= rtol) ? PT_OK : PT_ENOTCONV;
+}
+// The same transposed solve by defect correction: FP64 residual F(lambda) =
+// J_F lambda - xbar (the stage residual with gravity off, the history term
+// -xbar_V and old pressures from k_adj_oldvalues), FP32 PT sweeps on the
+// correction (their own right-hand side is the residual), lambda += d in
+// FP64.  lambda ends in copy 0.  Needs beta_d > 0 and the mixed workspace.
+pt_status mixed_transposed_solve(pt_grid* g, const double* lp, const double* kc, const double* eta,
+                                 const double* mus, double rtol, double eta_in, int64_t max_iter, int64_t* iters) {
+    const int64_t box_bytes = mx_box(g) * (int64_t)sizeof(double);
+    hipError_t e = hipMemsetAsync(ad(g, 0), 0, 8 * box_bytes, g->stream);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(g->mws, 0, 16 * mx_box(g) * (int64_t)sizeof(float), g->stream);
+    if (e == hipSuccess)
+        e = launch_adj_oldvalues(g->geom, g->coef, ad(g, AD_RHS + 3), ad(g, AD_RHS + 4), ad(g, AD_MXOLD),
+                                 ad(g, AD_MXOLD + 1), g->stream);
+    if (e != hipSuccess) return hip_fail(g, e, "mixed adjoint set-up");
+    MixedTarget t;
+    t.resid = SweepPtrs<double>{};
+    SweepPtrs<double>& p = t.resid;
+    p.vx = ad(g, 0); p.vy = ad(g, 1); p.vz = ad(g, 2); p.pt = ad(g, 3); p.pf = ad(g, 4);
+    p.lp = lp; p.kc = kc; p.eta = eta; p.mus = mus;
+    p.pto = ad(g, AD_MXOLD); p.pfo = ad(g, AD_MXOLD + 1);
+    p.fox = ad(g, AD_RHS); p.foy = ad(g, AD_RHS + 1); p.foz = ad(g, AD_RHS + 2);
+    t.m = MixedPtrs{};
+    t.m.vx = ad(g, 0); t.m.vy = ad(g, 1); t.m.vz = ad(g, 2); t.m.pt = ad(g, 3); t.m.pf = ad(g, 4);
+    t.m.lp = lp; t.m.kc = kc; t.m.eta = eta; t.m.mus = mus;
+    t.coef = g->coef;
+    t.coef.rhofg = 0.0;
+    t.coef.rhosg = 0.0;
+    t.coef.rhobg = 0.0;
+    t.coef.buoy = 0.0;
+    double rv = 0.0, rp = 0.0, rho = 0.0;
+    bool ref_set = false;
+    int copy = 0;
+    int32_t outer = 0;
+    return mixed_core(g, t, rtol, eta_in, max_iter, PICARD_MAX_CORRECTIONS, rv, rp, ref_set, copy, iters, &outer,
+                      &rho);
 }
 }  // namespace
 
@@ -879,19 +971,28 @@ namespace {
 constexpr int CKPT_FIELDS[] = {PT_VX, PT_VY, PT_VZ, PT_PT, PT_PF, PT_LP, PT_RX, PT_RY, PT_RZ,
                                PT_SXX, PT_SYY, PT_SZZ, PT_SXY, PT_SXZ, PT_SYZ};
 constexpr int CKPT_NBOX = sizeof(CKPT_FIELDS) / sizeof(CKPT_FIELDS[0]);
+// Inner tolerance of the mixed solves of a run adjoint.
+constexpr double ADJ_MIXED_ETA_IN = 1e-4;
 
-size_t tape_boxes(int32_t n_steps, int32_t n_picard, int32_t checkpoint) {
-    return checkpoint ? (size_t)n_steps * CKPT_NBOX + (size_t)n_picard * TAPE_NBOX
+size_t tape_boxes(int32_t n_steps, int32_t n_picard, int32_t options) {
+    return (options & PT_ADJ_CHECKPOINT) ? (size_t)n_steps * CKPT_NBOX + (size_t)n_picard * TAPE_NBOX
                       : (size_t)n_steps * n_picard * TAPE_NBOX;
 }
 
 // One Picard step from the present state, recording its stages at rec(p, b).
 template <typename Rec>
 pt_status recorded_step(pt_grid* g, int n, int32_t n_picard, double rtol, int64_t max_iter, Rec rec,
-                        int64_t* fit, int32_t phase) {
+                        int64_t* fit, int32_t phase, bool mixed) {
     const int64_t box = mx_box(g);
     pt_status st = pt_begin_step(g, n >= 1 ? 1 : 0);
     if (st != PT_OK) return st;
+    if (mixed) {
+        // the FP32 damped residual starts each step at zero, so that a step
+        // recomputed from its checkpoint repeats the recorded one bit for bit
+        hipError_t e = hipMemsetAsync(g->mws, 0, 16 * box * (int64_t)sizeof(float), g->stream);
+        if (e != hipSuccess) return hip_fail(g, e, "mixed step set-up");
+        g->mx_copy = 0;
+    }
     for (int p = 0; p < n_picard; ++p) {
         st = refresh_impl(g, 1.0, 1.0);
         if (st != PT_OK) return st;
@@ -902,7 +1003,12 @@ pt_status recorded_step(pt_grid* g, int n, int32_t n_picard, double rtol, int64_
         }
         int64_t it = 0;
         double rho = 0.0;
-        st = pt_solve_linear(g, rtol, max_iter, &it, &rho);
+        if (mixed) {
+            int32_t outer = 0;
+            st = pt_solve_mixed(g, rtol, ADJ_MIXED_ETA_IN, max_iter, PICARD_MAX_CORRECTIONS, &it, &outer, &rho);
+        } else {
+            st = pt_solve_linear(g, rtol, max_iter, &it, &rho);
+        }
         *fit += it;
         if (st == PT_ENOTCONV) return fail(g, PT_ENOTCONV, "a forward stage did not reach rtol");
         if (st != PT_OK) return st;
@@ -932,14 +1038,14 @@ pt_status checkpoint_copy(pt_grid* g, double* ck, bool save) {
 
 extern "C" {
 
-pt_status pt_adjoint_tape_size(const pt_grid* g, int32_t n_steps, int32_t n_picard, int32_t checkpoint,
+pt_status pt_adjoint_tape_size(const pt_grid* g, int32_t n_steps, int32_t n_picard, int32_t options,
                                size_t* bytes) {
     if (!g || !bytes || n_steps < 1 || n_picard < 1) return PT_EINVAL;
-    *bytes = tape_boxes(n_steps, n_picard, checkpoint) * (size_t)mx_box(g) * sizeof(double);
+    *bytes = tape_boxes(n_steps, n_picard, options) * (size_t)mx_box(g) * sizeof(double);
     return PT_OK;
 }
 
-pt_status pt_adjoint_run(pt_grid* g, int32_t n_steps, int32_t n_picard, int32_t checkpoint, double rtol,
+pt_status pt_adjoint_run(pt_grid* g, int32_t n_steps, int32_t n_picard, int32_t options, double rtol,
                          double adj_rtol, int64_t max_iter, const int64_t* sensors, int32_t ns, const double* d_obs,
                          void* tape, size_t tape_bytes, void* grad_dev, double* J, int64_t* fwd_iters,
                          int64_t* adj_iters) {
@@ -951,10 +1057,18 @@ pt_status pt_adjoint_run(pt_grid* g, int32_t n_steps, int32_t n_picard, int32_t 
     if (g->prm.flags & (PT_F_POWERLAW | PT_F_DPCAP | PT_F_MECHOFF))
         return fail(g, PT_EINVAL, "the run adjoint needs the Newtonian viscosity law with mechanics on");
     if (!(g->prm.flags & PT_F_K0FIELD)) return fail(g, PT_EINVAL, "the run adjoint needs a k0 field");
+    if (options & ~(PT_ADJ_CHECKPOINT | PT_ADJ_MIXED)) return fail(g, PT_EINVAL, "unknown run-adjoint option");
+    const bool checkpoint = (options & PT_ADJ_CHECKPOINT) != 0;
+    const bool mixed = (options & PT_ADJ_MIXED) != 0;
+    if (mixed) {
+        if (!(g->prm.beta_d > 0.0)) return fail(g, PT_EINVAL, "the mixed run adjoint needs beta_d > 0");
+        st = mixed_ready(g);
+        if (st != PT_OK) return st;
+    }
     if (!g->aws) return fail(g, PT_EINVAL, "adjoint workspace not bound");
     if (ns < 1 || ns > g->aws_sensors) return fail(g, PT_EINVAL, "sensor count outside the workspace capacity");
     size_t need = 0;
-    pt_adjoint_tape_size(g, n_steps, n_picard, checkpoint, &need);
+    pt_adjoint_tape_size(g, n_steps, n_picard, options, &need);
     if (tape_bytes < need) return fail(g, PT_EINVAL, "tape too small");
     if ((reinterpret_cast<uintptr_t>(tape) | reinterpret_cast<uintptr_t>(grad_dev)) & 255u)
         return fail(g, PT_EINVAL, "tape or gradient buffer unaligned");
@@ -981,7 +1095,7 @@ pt_status pt_adjoint_run(pt_grid* g, int32_t n_steps, int32_t n_picard, int32_t 
             refreshed_at[n] = g->refreshed ? 1 : 0;
         }
         st = recorded_step(g, n, n_picard, rtol, max_iter, [&](int p, int b) { return tp(n, p, b); }, &fit,
-                           PT_PROGRESS_FORWARD);
+                           PT_PROGRESS_FORWARD, mixed);
         if (st != PT_OK) return st;
     }
     double Jv = 0.0;
@@ -1020,7 +1134,7 @@ pt_status pt_adjoint_run(pt_grid* g, int32_t n_steps, int32_t n_picard, int32_t 
             g->refreshed = refreshed_at[n] != 0;
             int64_t rit = 0;
             st = recorded_step(g, n, n_picard, rtol, max_iter, [&](int p, int b) { return tp(n, p, b); }, &rit,
-                               PT_PROGRESS_RECOMPUTE);
+                               PT_PROGRESS_RECOMPUTE, mixed);
             if (st != PT_OK) return st;
         }
         for (int p = n_picard - 1; p >= 0; --p) {
@@ -1034,7 +1148,10 @@ pt_status pt_adjoint_run(pt_grid* g, int32_t n_steps, int32_t n_picard, int32_t 
             if (e != hipSuccess) return hip_fail(g, e, "run adjoint porosity");
             int cp = 0;
             const int64_t ait0 = ait;
-            st = transposed_solve(g, a.kc, a.mus, adj_rtol, max_iter, &cp, &ait, &arho);
+            if (mixed)
+                st = mixed_transposed_solve(g, a.lp, a.kc, a.eta, a.mus, adj_rtol, ADJ_MIXED_ETA_IN, max_iter, &ait);
+            else
+                st = transposed_solve(g, a.kc, a.mus, adj_rtol, max_iter, &cp, &ait, &arho);
             if (st == PT_ENOTCONV) return fail(g, PT_ENOTCONV, "a transposed stage solve did not reach adj_rtol");
             if (st != PT_OK) return st;
             const int lb0 = cp ? 8 : 0;

@@ -169,6 +169,8 @@ hipError_t launch_adj_porosity(const Geom& g, const Coef& c, const AdjPtrs& a, h
 hipError_t launch_adj_coef(const Geom& g, const Coef& c, const AdjPtrs& a, hipStream_t s);
 hipError_t launch_adj_step(const Geom& g, const Coef& c, const AdjPtrs& a, hipStream_t s);
 hipError_t launch_adj_history(const Geom& g, const Coef& c, const AdjPtrs& a, hipStream_t s);
+hipError_t launch_adj_oldvalues(const Geom& g, const Coef& c, const double* rpt, const double* rpf, double* pto,
+                                double* pfo, hipStream_t s);
 hipError_t launch_absmax5(const Geom& g, const double* const* f, double* partials, int64_t nblocks,
                           hipStream_t s);
 

@@ -298,16 +298,20 @@ class Grid:
         _check(self.lib, self.h, self.lib.pt_set_progress(self.h, self._progress_cb, None), "progress")
 
     def adjoint_run(self, sensors, d_obs, n_steps, n_picard, rtol=1e-12, adj_rtol=None, max_iter=2_000_000,
-                    checkpoint=False):
+                    checkpoint=False, mixed=False):
         """Recorded Picard run of n_steps x n_picard stages from the present
         state and its adjoint (see pt_adjoint_run): returns J, dJ/d(ln k0)
         (device tensor view, cells), forward and transposed sweep counts.
-        checkpoint: keep step checkpoints and recompute the stages in reverse."""
+        checkpoint: keep step checkpoints and recompute the stages in reverse;
+        mixed: FP32 sweeps inside FP64 defect correction for every solve."""
         adj_rtol = rtol if adj_rtol is None else adj_rtol
         self.enable_adjoint(max(64, len(sensors)))
+        options = (abi.ADJ_CHECKPOINT if checkpoint else 0) | (abi.ADJ_MIXED if mixed else 0)
+        if mixed:
+            self.enable_mixed()
         nbytes = C.c_size_t()
-        _check(self.lib, self.h, self.lib.pt_adjoint_tape_size(self.h, int(n_steps), int(n_picard),
-                                                               int(bool(checkpoint)), C.byref(nbytes)),
+        _check(self.lib, self.h, self.lib.pt_adjoint_tape_size(self.h, int(n_steps), int(n_picard), options,
+                                                               C.byref(nbytes)),
                "tape size")
         self.tape_bytes = nbytes.value
         with torch.cuda.stream(self.stream):
@@ -318,7 +322,7 @@ class Grid:
         fit = C.c_int64()
         ait = C.c_int64()
         st = _check(self.lib, self.h, self.lib.pt_adjoint_run(
-            self.h, int(n_steps), int(n_picard), int(bool(checkpoint)), float(rtol), float(adj_rtol), int(max_iter),
+            self.h, int(n_steps), int(n_picard), options, float(rtol), float(adj_rtol), int(max_iter),
             s_arr.ctypes.data_as(C.POINTER(C.c_int64)), len(s_arr), d_arr.ctypes.data_as(C.POINTER(C.c_double)),
             C.c_void_p(tape.data_ptr()), nbytes.value, C.c_void_p(self.grad_buf.data_ptr()),
             C.byref(J), C.byref(fit), C.byref(ait)), "adjoint_run")

@@ -123,3 +123,28 @@ def test_run_autograd_function():
     fd = (Jp - Jm) / (2 * h)
     print("directional", dd, fd, flush=True)
     assert abs(dd - fd) <= 1e-6 * abs(fd)
+
+
+def test_run_adjoint_mixed_precision():
+    # every solve of the run (forward stages and transposed stages) by FP32
+    # sweeps inside FP64 defect correction, to the same tolerances: the same
+    # gradient as the FP64 run adjoint; with step checkpoints, bit for bit the
+    # mixed run on a full tape
+    n, steps, stages, rtol = 16, 2, 3, 1e-11
+    cfg, phi, logk0, sensors = _problem(n, seed=10)
+    d_obs = np.full(len(sensors), 1e-4)
+    g64 = _grid(cfg, phi, logk0)
+    J64, grad64, fit64, ait64 = g64.adjoint_run(sensors, d_obs, steps, stages, rtol=rtol)
+    grad64 = grad64.cpu().numpy().copy()
+    gmx = _grid(cfg, phi, logk0)
+    Jmx, gradmx, fitmx, aitmx = gmx.adjoint_run(sensors, d_obs, steps, stages, rtol=rtol, mixed=True)
+    gradmx = gradmx.cpu().numpy().copy()
+    err = np.abs(gradmx - grad64).max() / np.abs(grad64).max()
+    print("J", J64, Jmx, "sweeps fp64", fit64, ait64, "mixed", fitmx, aitmx, "grad rel diff", err, flush=True)
+    assert abs(Jmx - J64) <= 1e-8 * abs(J64)
+    assert err <= 1e-7
+    gck = _grid(cfg, phi, logk0)
+    Jck, gradck, fitck, aitck = gck.adjoint_run(sensors, d_obs, steps, stages, rtol=rtol, mixed=True,
+                                                checkpoint=True)
+    assert Jck == Jmx and aitck == aitmx
+    assert np.array_equal(gradck.cpu().numpy(), gradmx)
