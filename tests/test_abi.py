@@ -61,3 +61,42 @@ def test_create_validates_arguments(lib):
     finally:
         lib.pt_destroy(h)
     assert lib.pt_status_str(-3) == b"diverged (non-finite norm)"
+
+
+def test_driver_and_adjoint_entry_points_validate_on_the_host(lib):
+    p = abi.params_from(inputs.Physics(), True)
+    h = C.c_void_p()
+    assert lib.pt_create(6, 5, 4, 32, C.byref(p), C.byref(h)) == 0
+    try:
+        box = lib.pt_field_elems(h) * 8
+        sweeps, rho = C.c_int64(), C.c_double()
+        # argument checks
+        assert lib.pt_picard_step(h, 0, 0, 1e-8, 100, 0, 1e-4, C.byref(sweeps), C.byref(rho)) == -1
+        assert lib.pt_picard_step(h, 0, 2, 0.0, 100, 0, 1e-4, C.byref(sweeps), C.byref(rho)) == -1
+        assert lib.pt_picard_step(h, 0, 2, 1e-8, 100, 1, 1.5, C.byref(sweeps), C.byref(rho)) == -1
+        # nothing bound: refused before any launch
+        assert lib.pt_picard_step(h, 0, 2, 1e-8, 100, 0, 1e-4, C.byref(sweeps), C.byref(rho)) == -1
+        inner, outer = C.c_int64(), C.c_int32()
+        assert lib.pt_solve_mixed(h, 1e-8, 1e-4, 10, 2, C.byref(inner), C.byref(outer), C.byref(rho)) == -1
+        assert lib.pt_solve_linear(h, 1e-8, 10, C.byref(inner), C.byref(rho)) == -1
+        # workspaces: sizes and binding checks
+        sz = C.c_size_t()
+        assert lib.pt_mixed_workspace_size(h, C.byref(sz)) == 0 and sz.value == 24 * box // 2
+        assert lib.pt_bind_mixed_workspace(h, C.c_void_p(0x1008), sz.value) == -1
+        assert lib.pt_adjoint_workspace_size(h, 0, C.byref(sz)) == -1
+        assert lib.pt_adjoint_workspace_size(h, 16, C.byref(sz)) == 0 and sz.value >= 40 * box
+        # tape sizes: every stage (8 boxes), or step checkpoints (15) + one step's stages
+        assert lib.pt_adjoint_tape_size(h, 3, 5, 0, C.byref(sz)) == 0 and sz.value == 3 * 5 * 8 * box
+        assert lib.pt_adjoint_tape_size(h, 3, 5, abi.ADJ_CHECKPOINT, C.byref(sz)) == 0
+        assert sz.value == (3 * 15 + 5 * 8) * box
+        assert lib.pt_adjoint_tape_size(h, 0, 5, 0, C.byref(sz)) == -1
+        J, fit, ait = C.c_double(), C.c_int64(), C.c_int64()
+        sensors = (C.c_int64 * 2)(1, 2)
+        d_obs = (C.c_double * 2)(0.0, 0.0)
+        assert lib.pt_adjoint_run(h, 1, 1, 0, 1e-8, 1e-8, 100, None, 2, d_obs, C.c_void_p(0x1000), 1 << 20,
+                                  C.c_void_p(0x1000), C.byref(J), C.byref(fit), C.byref(ait)) == -1
+        assert lib.pt_adjoint_run(h, 1, 1, 0, 1e-8, 1e-8, 100, sensors, 2, d_obs, C.c_void_p(0x1000), 1 << 20,
+                                  C.c_void_p(0x1000), C.byref(J), C.byref(fit), C.byref(ait)) == -1
+        assert lib.pt_set_progress(h, abi.PROGRESS_FN(), None) == 0
+    finally:
+        lib.pt_destroy(h)
