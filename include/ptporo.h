@@ -16,9 +16,10 @@
  * ------------------------------
  * Ownership.  The caller owns every device buffer and the stream; the library
  *   owns only the handle.  It never allocates device memory: the scratch it
- *   needs (per-block partial maxima) is a caller buffer bound with
- *   pt_bind_workspace.  Bound pointers must stay valid while the handle uses
- *   them.
+ *   needs is in caller buffers bound with pt_bind_workspace (and, for the
+ *   mixed-precision solves and the adjoints, pt_bind_mixed_workspace and
+ *   pt_bind_adjoint_workspace; the run adjoint's tape is an argument).
+ *   Bound pointers must stay valid while the handle uses them.
  * Layout.  Every field is an FP64 array in one common padded box layout:
  *   element (i, j, k) of any staggered field is at offset
  *   (k * (ny + 1) + j) * row_pitch + i, x fastest, so each field buffer holds
@@ -142,8 +143,10 @@ int64_t pt_field_elems(const pt_grid* g);
  * 1 for the double-buffered fields (PT_VX .. PT_RZ) and 0 otherwise. */
 pt_status pt_bind_field(pt_grid* g, int32_t field, int32_t copy, void* dev_ptr);
 
-/* Scratch for per-block partial maxima: query the size, then bind a device
- * buffer of at least that many bytes (256-byte aligned). */
+/* Workspace of the solver: per-block partial maxima of the norms, the eight
+ * reduced norms and three padded-box scratch fields of the refresh (edge
+ * stresses and history terms).  Query the size, then bind a device buffer of
+ * at least that many bytes (256-byte aligned). */
 pt_status pt_workspace_size(const pt_grid* g, size_t* bytes);
 pt_status pt_bind_workspace(pt_grid* g, void* dev_ptr, size_t bytes);
 

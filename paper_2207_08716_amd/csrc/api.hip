@@ -337,7 +337,8 @@ pt_status pt_workspace_size(const pt_grid* g, size_t* bytes) {
 
 pt_status pt_bind_workspace(pt_grid* g, void* dev_ptr, size_t bytes) {
     if (!g) return PT_EINVAL;
-    if (!dev_ptr || bytes < ws_needed(g)) return fail(g, PT_EINVAL, "workspace missing or too small");
+    if (!dev_ptr || (reinterpret_cast<uintptr_t>(dev_ptr) & 255u) || bytes < ws_needed(g))
+        return fail(g, PT_EINVAL, "workspace missing, unaligned or too small");
     g->ws = dev_ptr;
     g->ws_bytes = bytes;
     return PT_OK;
