@@ -65,10 +65,19 @@ def cpu_baseline(cfg, fields, n_iter: int = 2):
     t2 = time.perf_counter()
     t_it = (t2 - t1) / n_iter
     del o
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {
         "value": round(teff.t_eff_gbs(cfg.ncell, 8, t_it), 3),
         "unit": "GB/s",
         "cores": oracle.num_threads(),
+        "cpu_model": model,
         "kind": "oracle",
         "sample": f"{n_iter} thesis-schedule PT iterations of the same {cfg.nx}^3 FP64 workload "
                   f"after one warm-up iteration (setup {t1 - t0:.1f} s); t_it = {t_it:.3f} s",
