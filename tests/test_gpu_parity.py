@@ -224,3 +224,24 @@ def test_parity_ragged_linear_and_correction_sweeps(shape):
     worst = {k: _rel(g.get(k), o.f[k]) for k in ("vx", "vy", "vz", "pt", "pf")}
     print(worst, flush=True)
     assert max(worst.values()) <= 1e-5, worst
+
+
+def test_tilings_give_bitwise_equal_fields():
+    """The sweeps with norms run on 64x8 blocks, the plain ones on 66-wide
+    blocks of 8 or 10 rows: every cell's arithmetic is the same, so a run
+    that takes the norms at every iteration equals, bit for bit, one that
+    never does (thesis and linear sweeps, ragged grid)."""
+    import dataclasses
+    cfg = inputs.config_fp64_picard(8)
+    cfg = dataclasses.replace(cfg, nx=70, ny=23, nz=19, name="tilings")
+    cfg.phys = cfg.phys.replace(lx=70 / 40, ly=23 / 40, lz=19 / 40)
+    out = []
+    for norms in (False, True):
+        g, _o = _pair(cfg)
+        g.begin_step(False)
+        g.refresh()
+        for it in range(30):
+            g.iteration(update_lp=(it < 20), norms=norms)
+        out.append({n: g.get(n) for n in STATE})
+    for n in STATE:
+        assert np.array_equal(out[0][n], out[1][n]), n

@@ -462,3 +462,55 @@ def test_inputs_reproducible():
     assert 2.5 < phi.max() / c.phys.phi0 < 3.0 * (1 + 1e-3)
     g = inputs.gaussian_random_field((32, 32, 32), (1, 1, 1), 0.1, 4)
     assert abs(g.mean()) < 1e-12 and abs(g.std() - 1) < 1e-12
+
+
+def test_porosity_step_closed_forms():
+    """Eq (22) in log space, L = ln(1 - phi): d L/dt = -(1/(1-phi)) d^s phi/dt
+    = beta_phi d(Pt - Pf)/dt + (Pt - Pf)/eta_phi - V.grad(1-phi) terms.
+    (i) with a constant effective pressure Pt - Pf = D, no storage change and
+    V = 0, L grows linearly, L(t) = L0 + t D/eta (the exact solution; the
+    explicit step is exact); (ii) a uniform pressure change dPf with Pt fixed
+    lowers L by beta_phi dPf; (iii) a uniform velocity U in x over a solid
+    fraction linear in x gives the advection rate U ds/dx away from the
+    boundaries."""
+    n = 6
+    ph = inputs.Physics()
+    o = make(ph, n)
+    eta = 2.5
+    o.f["eta"][...] = eta
+    D = 0.3
+    o.f["pt"][...] = 1.0 + D
+    o.f["pf"][...] = 1.0
+    o.f["pto"][...] = o.f["pt"]
+    o.f["pfo"][...] = o.f["pf"]
+    L0 = o.f["lp"].copy()
+    for step in range(1, 4):
+        o.f["lpo"][...] = o.f["lp"]
+        o.porosity_step()
+        assert np.allclose(o.f["lp"], L0 + step * ph.dt * D / eta, rtol=0, atol=1e-15)
+    # (ii) storage: Pf - Pfo = dp, Pt = Pto, Pt = Pf (no viscous term)
+    o.f["lp"][...] = L0
+    o.f["lpo"][...] = L0
+    dp = 0.05
+    o.f["pt"][...] = 1.0
+    o.f["pto"][...] = 1.0
+    o.f["pfo"][...] = 1.0 - dp
+    o.f["pf"][...] = 1.0
+    o.f["pt"][...] = 1.0
+    o.porosity_step()
+    assert np.allclose(o.f["lp"], L0 - ph.beta_phi * dp, rtol=0, atol=1e-15)
+    # (iii) advection: s = 1 - phi linear in x, Vx = U on interior x-faces
+    x = (np.arange(n) + 0.5) / n
+    s = 0.98 + 0.01 * x
+    o.f["lp"][...] = np.log(s)[None, None, :]
+    o.f["lpo"][...] = o.f["lp"]
+    o.f["pto"][...] = o.f["pt"]
+    o.f["pfo"][...] = o.f["pf"]
+    U = 0.7
+    o.f["vx"][...] = U
+    o.f["vx"][:, :, 0] = 0.0
+    o.f["vx"][:, :, -1] = 0.0
+    Lb = o.f["lp"].copy()
+    o.porosity_step()
+    rate = -(o.f["lp"] - Lb) / ph.dt
+    assert np.allclose(rate[:, :, 1:-1], U * 0.01, rtol=1e-12, atol=0)
