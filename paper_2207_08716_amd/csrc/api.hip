@@ -303,8 +303,7 @@ pt_status pt_create(int32_t nx, int32_t ny, int32_t nz, int64_t row_pitch, const
     g->geom.nz = nz;
     g->geom.P = row_pitch;
     g->geom.S = row_pitch * (int64_t)(ny + 1);
-    g->geom.kz = KZ_MAX;
-    g->geom.kz = choose_kz(g->geom);
+    g->geom.kz = KZ_MAX;   // each sweep variant sets its own chunk at launch
     g->prm = *params;
     std::memset(g->f, 0, sizeof(g->f));
     std::memset(g->cur, 0, sizeof(g->cur));

@@ -503,8 +503,9 @@ __global__ __launch_bounds__(256) void k_reduce_max(const double* __restrict__ p
 template <typename T, int MODE, bool NORMS>
 void launch_sweep(const Geom& g, const Coef& c, const SweepPtrs<T>& p, hipStream_t s) {
     constexpr int W = sweep_bx<MODE, NORMS>(), H = sweep_by<T, MODE, NORMS>();
+    const Geom v = sweep_geom(g, W, H);
     hipLaunchKernelGGL((k_sweep<T, MODE, NORMS>), dim3((unsigned)iter_grid_blocks(g, W, H)), dim3(W, H, 1), 0, s,
-                       g, c, p);
+                       v, c, p);
 }
 
 hipError_t launch_iteration(const Geom& g, const Coef& c, const SweepPtrs<double>& p, int mode, int norms,

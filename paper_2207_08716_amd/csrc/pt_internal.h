@@ -2,6 +2,8 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 #include <stdint.h>
 
 #include "ptporo.h"
@@ -13,7 +15,7 @@ struct Geom {
     int nx, ny, nz;
     int64_t P;   // row pitch (elements)
     int64_t S;   // plane pitch = (ny + 1) * P
-    int kz;      // planes per z chunk of the sweep (chosen at create time)
+    int kz;      // planes per z chunk of a sweep (set per sweep variant at launch)
 };
 
 // Physical and numerical constants, in the form the kernels use them.
@@ -72,24 +74,46 @@ constexpr int BX_NORMS = 64;
 constexpr int BY_NORMS = 8;
 constexpr int KZ_MAX = 64;
 
+constexpr int KZ_MIN = 4;
+constexpr int64_t GPU_CUS = 256;   // MI355X compute units (one sweep block each)
+
 inline int64_t tiles_xy(const Geom& g, int bx = BX, int by = BY) {
     return (int64_t)((g.nx + bx - 3) / (bx - 2)) * ((g.ny + by - 3) / (by - 2));
 }
 
-inline int64_t iter_grid_blocks(const Geom& g, int bx = BX, int by = BY) {
-    return tiles_xy(g, bx, by) * ((g.nz + g.kz - 1) / g.kz);
+// Planes per z chunk for a tiling: the sweep blocks occupy one CU each, so a
+// launch takes ceil(blocks / 256) rounds of (chunk + 2) plane steps (two
+// planes of halo and prefetch per chunk); the chunk minimising that wins,
+// the longer one on ties.
+inline int choose_kz(const Geom& g, int bx, int by) {
+    const int64_t t = tiles_xy(g, bx, by);
+    int best = KZ_MAX;
+    int64_t best_cost = -1;
+    for (int kz = KZ_MAX; kz >= KZ_MIN; kz /= 2) {
+        const int64_t blocks = t * ((g.nz + kz - 1) / kz);
+        const int64_t cost = ((blocks + GPU_CUS - 1) / GPU_CUS) * (std::min(kz, g.nz) + 2);
+        if (best_cost < 0 || cost < best_cost) {
+            best = kz;
+            best_cost = cost;
+        }
+    }
+    return best;
+}
+
+// The geometry of one sweep variant: its z chunk set.
+inline Geom sweep_geom(const Geom& g, int bx, int by) {
+    Geom v = g;
+    v.kz = choose_kz(g, bx, by);
+    return v;
+}
+
+inline int64_t iter_grid_blocks(const Geom& g, int bx, int by) {
+    const Geom v = sweep_geom(g, bx, by);
+    return tiles_xy(v, bx, by) * ((v.nz + v.kz - 1) / v.kz);
 }
 
 // Blocks that write per-block norm maxima (size of the partials area).
 inline int64_t norm_blocks(const Geom& g) { return iter_grid_blocks(g, BX_NORMS, BY_NORMS); }
-
-// Longest z chunk that still gives the 256 CUs a few blocks each (short
-// chunks cost one extra halo plane per chunk).
-inline int choose_kz(const Geom& g) {
-    int kz = KZ_MAX;
-    while (kz > 8 && tiles_xy(g) * ((g.nz + kz - 1) / kz) < 1536) kz /= 2;
-    return kz;
-}
 
 // Launchers (defined in the .hip files).
 hipError_t launch_iteration(const Geom& g, const Coef& c, const SweepPtrs<double>& p, int mode,
