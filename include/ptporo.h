@@ -251,8 +251,10 @@ pt_status pt_residual(pt_grid* g);
  * stop when rho (as in pt_solve_linear, same step reference) <= rtol; solve
  * A d = -r by FP32 PT sweeps from d = 0 (the damped residual of d carried
  * over from the previous correction) until the correction residual falls
- * to eta_in times r, stops improving (no new 1 % minimum in 40 checks: the
- * FP32 round-off floor) or max_inner sweeps, checked every nup sweeps;
+ * to eta_in times r or to rtol/2 on the scale of rho (so that the last
+ * correction solves only the gap left to rtol), stops improving (no new 1 %
+ * minimum in 40 checks: the FP32 round-off floor) or max_inner sweeps,
+ * checked every nup sweeps;
  * x += d in FP64 }.  At most max_outer corrections.  Synchronises.
  * PT_ENOTCONV if rtol is not met (calling again continues). */
 pt_status pt_solve_mixed(pt_grid* g, double rtol, double eta_in, int64_t max_inner, int32_t max_outer,

@@ -587,7 +587,8 @@ struct MixedTarget {
 // Defect correction: repeat { r = FP64 residual of x; stop when rho <= rtol
 // (reference: ref_v/ref_p, set from the first residual if !ref_set); FP32
 // PT sweeps on A d = -r from d = 0, the damped residual of d carried over in
-// correction copy `copy`; x += d }.
+// correction copy `copy`, until the residual of d is eta_in times r, or
+// rtol/2 on the outer scale, or stalls; x += d }.
 pt_status mixed_core(pt_grid* g, const MixedTarget& t, double rtol, double eta_in, int64_t max_inner,
                      int32_t max_outer, double& ref_v, double& ref_p, bool& ref_set, int& copy,
                      int64_t* inner_iters, int32_t* outer_iters, double* rho) {
@@ -607,6 +608,10 @@ pt_status mixed_core(pt_grid* g, const MixedTarget& t, double rtol, double eta_i
     // the inner solve stops when its residual has not reached a new minimum
     // (by 1 %) for this many checks: FP32 cannot go below its round-off level
     const int stall_checks = 40;
+    // ... and once x + d would meet the outer tolerance with this margin: the
+    // last correction of a solve needs only the gap left to rtol, not a full
+    // eta_in reduction
+    const double target_margin = 0.5;
     double r = INFINITY;
     int64_t inner_total = 0;
     int32_t outer = 0;
@@ -647,7 +652,7 @@ pt_status mixed_core(pt_grid* g, const MixedTarget& t, double rtol, double eta_i
                 st = read_norms(g, &ni);
                 if (st != PT_OK) return st;
                 const double ri = group_rho(ni, gv, gp);
-                if (ri <= eta_in) break;
+                if (ri <= eta_in || group_rho(ni, ref_v, ref_p) <= target_margin * rtol) break;
                 if (ri < 0.99 * best) {
                     best = ri;
                     since_best = 0;
