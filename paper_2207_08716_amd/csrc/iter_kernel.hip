@@ -49,8 +49,9 @@ constexpr int sweep_bx() {
     return (NORMS || MODE == MD_RESID) ? BX_NORMS : BX;
 }
 // Block height: taller tiles re-read fewer halo rows but need registers for
-// more waves per CU; the heights below are the tallest that each variant fits
-// without spilling (measured fastest at 511^3).
+// more waves per CU, and the number of tiles sets how full the last round of
+// blocks is; the heights below fit each variant's registers without spilling
+// and were measured fastest at 511^3.
 template <typename T, int MODE, bool NORMS>
 constexpr int sweep_by() {
     if (NORMS || MODE == MD_RESID) return BY_NORMS;
@@ -93,6 +94,7 @@ template <typename T, int MODE, bool NORMS>
 __global__ __launch_bounds__((sweep_bx<MODE, NORMS>() * sweep_by<T, MODE, NORMS>())) void k_sweep(Geom g, Coef cd, SweepPtrs<T> p) {
     constexpr int W = sweep_bx<MODE, NORMS>();
     constexpr int H = sweep_by<T, MODE, NORMS>();
+    static_assert(W * H <= 1024, "a block holds at most 1024 threads");
     constexpr bool UPD_LP = (MODE == MD_THESIS);
     constexpr bool RESID = (MODE == MD_RESID);
     constexpr bool CORR = (MODE == MD_CORR);
@@ -109,7 +111,26 @@ __global__ __launch_bounds__((sweep_bx<MODE, NORMS>() * sweep_by<T, MODE, NORMS>
     const int by = (int)((Tt / gx) % gy);
     const int bz = (int)(Tt / ((int64_t)gx * gy));
 
-    const int tx = threadIdx.x, ty = threadIdx.y;
+    // Thread layout.  In 66-wide blocks, wave r (r < H) takes the 64 interior
+    // columns of row r, so that every load and store of a row is one whole,
+    // aligned 512-byte segment; the last wave takes the two side halo columns
+    // of all rows.  64-wide blocks map lanes to columns directly.
+    int tx, ty;
+    if constexpr (W == 64) {
+        tx = (int)threadIdx.x & 63;
+        ty = (int)threadIdx.x >> 6;
+    } else {
+        static_assert(W == 66, "sweep blocks are 64 or 66 wide");
+        const int L = threadIdx.x;
+        if (L < 64 * H) {
+            tx = 1 + (L & 63);
+            ty = L >> 6;
+        } else {
+            const int r = L - 64 * H;
+            tx = (r < H) ? 0 : W - 1;
+            ty = (r < H) ? r : r - H;
+        }
+    }
     const int i = bx * (W - 2) - 1 + tx;
     const int j = by * (H - 2) - 1 + ty;
     const int kz0 = bz * g.kz;
@@ -504,7 +525,7 @@ template <typename T, int MODE, bool NORMS>
 void launch_sweep(const Geom& g, const Coef& c, const SweepPtrs<T>& p, hipStream_t s) {
     constexpr int W = sweep_bx<MODE, NORMS>(), H = sweep_by<T, MODE, NORMS>();
     const Geom v = sweep_geom(g, W, H);
-    hipLaunchKernelGGL((k_sweep<T, MODE, NORMS>), dim3((unsigned)iter_grid_blocks(g, W, H)), dim3(W, H, 1), 0, s,
+    hipLaunchKernelGGL((k_sweep<T, MODE, NORMS>), dim3((unsigned)iter_grid_blocks(g, W, H)), dim3(W * H, 1, 1), 0, s,
                        v, c, p);
 }
 

@@ -63,13 +63,17 @@ constexpr int NNORM = 8;
 // output tile plus one halo column/row on every side and marches in z.
 // BX = 66 makes the output tile 64 columns wide: its rows start on 512-byte
 // boundaries of the padded rows (whole cache lines written) and n = 2^k - 1
-// grids fill their last tile; the block is 8 1/4 waves (528 threads).  The
-// variants that also reduce norms use BX_NORMS = 64 (8 whole waves).  Every
-// cell's arithmetic is the same in both tilings.
+// grids fill their last tile; each row's 64 interior columns are one wave,
+// the side halo columns of all rows one more (partial) wave.  The variants
+// that also reduce norms use BX_NORMS = 64 (whole waves).  Every cell's
+// arithmetic is the same in both tilings.  Heights: the tallest tile whose
+// waves fit the variant's registers is not always the fastest, since the
+// number of tiles decides how full the last round of blocks is; measured
+// at 511^3 (8-row tiles: 86 tile rows, 10-row tiles: 64).
 constexpr int BX = 66;
-constexpr int BY = 8;          // thesis sweep
+constexpr int BY = 10;         // thesis sweep
 constexpr int BY_LINEAR = 10;  // linear and FP64 correction sweeps
-constexpr int BY_CORR32 = 12;  // FP32 correction sweep
+constexpr int BY_CORR32 = 14;  // FP32 correction sweep
 constexpr int BX_NORMS = 64;
 constexpr int BY_NORMS = 8;
 constexpr int KZ_MAX = 64;

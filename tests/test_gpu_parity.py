@@ -198,7 +198,7 @@ def test_copy_kernel():
 
 @pytest.mark.parametrize("shape", [(70, 13, 41), (9, 27, 20)])
 def test_parity_ragged_linear_and_correction_sweeps(shape):
-    """The linear sweep (10-row tiles) and the FP32 correction sweep (12-row
+    """The linear sweep (10-row tiles) and the FP32 correction sweep (14-row
     tiles) on grids whose tiles end ragged in x and y: a fixed number of
     linear iterations against the oracle, then a mixed stage against the
     oracle's converged stage."""
@@ -227,8 +227,8 @@ def test_parity_ragged_linear_and_correction_sweeps(shape):
 
 
 def test_tilings_give_bitwise_equal_fields():
-    """The sweeps with norms run on 64x8 blocks, the plain ones on 66-wide
-    blocks of 8 or 10 rows: every cell's arithmetic is the same, so a run
+    """The sweeps with norms run on 64x8 blocks, the plain ones on 66x10
+    blocks with another thread layout: every cell's arithmetic is the same, so a run
     that takes the norms at every iteration equals, bit for bit, one that
     never does (thesis and linear sweeps, ragged grid)."""
     import dataclasses
