@@ -143,10 +143,9 @@ int64_t pt_field_elems(const pt_grid* g);
  * 1 for the double-buffered fields (PT_VX .. PT_RZ) and 0 otherwise. */
 pt_status pt_bind_field(pt_grid* g, int32_t field, int32_t copy, void* dev_ptr);
 
-/* Workspace of the solver: per-block partial maxima of the norms, the eight
- * reduced norms and three padded-box scratch fields of the refresh (edge
- * stresses and history terms).  Query the size, then bind a device buffer of
- * at least that many bytes (256-byte aligned). */
+/* Workspace of the solver: per-block partial maxima of the norms and the
+ * eight reduced norms (a few MB at the largest grids).  Query the size, then
+ * bind a device buffer of at least that many bytes (256-byte aligned). */
 pt_status pt_workspace_size(const pt_grid* g, size_t* bytes);
 pt_status pt_bind_workspace(pt_grid* g, void* dev_ptr, size_t bytes);
 

@@ -118,7 +118,6 @@ RefreshCoef make_refresh(const pt_grid* g, double r_eta, double r_mu) {
     return r;
 }
 
-int64_t ws_scratch_offset(const pt_grid* g);
 size_t ws_needed(const pt_grid* g);
 
 double* cur(pt_grid* g, int f) { return f < PT_NPING ? g->f[f][g->cur[f]] : g->f[f][0]; }
@@ -158,13 +157,6 @@ AuxPtrs aux(pt_grid* g) {
     a.mus = cur(g, PT_MUS);
     a.k0 = g->f[PT_K0][0];
     a.lp_o = alt(g, PT_LP);
-    if (g->ws) {
-        const int64_t box = g->geom.S * (int64_t)(g->geom.nz + 1);
-        double* base = static_cast<double*>(g->ws) + ws_scratch_offset(g);
-        a.scr0 = base;
-        a.scr1 = base + box;
-        a.scr2 = base + 2 * box;
-    }
     return a;
 }
 
@@ -180,16 +172,11 @@ pt_status check_ready(pt_grid* g) {
     return PT_OK;
 }
 
-// Workspace layout (doubles): [partials: n_blocks * 8][norms: 8][pad to 256 B]
-// [three padded-box scratch fields for the refresh passes].
-int64_t ws_scratch_offset(const pt_grid* g) {
-    const int64_t head = norm_blocks(g->geom) * NNORM + NNORM;
-    return (head + 31) / 32 * 32;
-}
-
+// Workspace layout (doubles): [partials: n_blocks * 8][norms: 8], padded to
+// a multiple of 256 bytes.
 size_t ws_needed(const pt_grid* g) {
-    const int64_t box = g->geom.S * (int64_t)(g->geom.nz + 1);
-    return (size_t)(ws_scratch_offset(g) + 3 * box) * sizeof(double);
+    const int64_t head = norm_blocks(g->geom) * NNORM + NNORM;
+    return (size_t)((head + 31) / 32 * 32) * sizeof(double);
 }
 
 pt_status refresh_impl(pt_grid* g, double r_eta, double r_mu) {

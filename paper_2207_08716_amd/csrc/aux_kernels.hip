@@ -124,21 +124,10 @@ __global__ __launch_bounds__(AB) void k_history(Geom g, Coef c, AuxPtrs a) {
     if (i < g.nx) a.syz[o] = se.yz(i, j, k);
 }
 
-// Refresh, pass 1: shear stresses of the present state on every edge, once
-// per edge, into scratch (xy, xz, yz), for the stress invariant.
-__global__ __launch_bounds__(AB) void k_refresh_edges(Geom g, Coef c, AuxPtrs a) {
-    Idx q;
-    if (!box_index(g, (int64_t)blockIdx.x * AB + threadIdx.x, q)) return;
-    const StressEval se{g, c, a};
-    const int i = q.i, j = q.j, k = q.k;
-    const int64_t o = at(g, i, j, k);
-    if (k < g.nz) a.scr0[o] = se.xy(i, j, k);
-    if (j < g.ny) a.scr1[o] = se.xz(i, j, k);
-    if (i < g.nx) a.scr2[o] = se.yz(i, j, k);
-}
-
-// Refresh, pass 2 (eqs (23)-(26)): k/mu_f, eta_phi and Mn at the cells.
-// mu_s itself is rewritten by the Fo passes (other cells still read it here).
+// Refresh of the lagged coefficients (eqs (23)-(26)) when the viscosity does
+// not depend on stress: k/mu_f, eta_phi and Mn at the cells from cell values
+// alone.  (With a power law or yield cap the tiled refresh kernel computes
+// the stress invariant and does the same updates.)
 __global__ __launch_bounds__(AB) void k_refresh(Geom g, Coef c, RefreshCoef r, AuxPtrs a) {
     Idx q;
     if (!box_index(g, (int64_t)blockIdx.x * AB + threadIdx.x, q)) return;
@@ -155,101 +144,10 @@ __global__ __launch_bounds__(AB) void k_refresh(Geom g, Coef c, RefreshCoef r, A
     const double R = (pf > pt) ? 1.0 / r.R0 : 1.0;
     const double eta_new = r.eta0 * mn * (r.phi0 / phi) * R;
     const double eta = r.first ? eta_new : exp(r.r_eta * log(eta_new) + (1.0 - r.r_eta) * log(a.eta[o]));
-
-    double mn_new = r.mu0;
-    if (r.powerlaw || r.dpcap) {
-        const StressEval se{g, c, a};
-        double txx, tyy, tzz;
-        se.normal(i, j, k, txx, tyy, tzz);
-        const double axy = 0.25 * (a.scr0[o] + a.scr0[at(g, i + 1, j, k)] + a.scr0[at(g, i, j + 1, k)] +
-                                   a.scr0[at(g, i + 1, j + 1, k)]);
-        const double axz = 0.25 * (a.scr1[o] + a.scr1[at(g, i + 1, j, k)] + a.scr1[at(g, i, j, k + 1)] +
-                                   a.scr1[at(g, i + 1, j, k + 1)]);
-        const double ayz = 0.25 * (a.scr2[o] + a.scr2[at(g, i, j + 1, k)] + a.scr2[at(g, i, j, k + 1)] +
-                                   a.scr2[at(g, i, j + 1, k + 1)]);
-        const double tii = sqrt(0.5 * (txx * txx + tyy * tyy + tzz * tzz) + axy * axy + axz * axz + ayz * ayz);
-        if (r.powerlaw) {
-            const double t = tii * r.tau0_inv;
-            const double tp = (r.n_pow == 3.0) ? t * t : pow(t, r.n_pow - 1.0);
-            mn_new = r.mu0 / (1.0 + tp);
-        }
-        if (r.dpcap) {
-            const double ty = fmax(r.coh_cos + (pt - pf) * r.sin_f, r.tau_y_min);
-            if (tii > ty) mn_new = fmin(mn_new, mn * ty / tii);
-        }
-    }
-    const double mnr = r.first ? mn_new : exp(r.r_mu * log(mn_new) + (1.0 - r.r_mu) * log(mn));
+    const double mnr = r.first ? r.mu0 : exp(r.r_mu * log(r.mu0) + (1.0 - r.r_mu) * log(mn));
     a.kc[o] = kc;
     a.eta[o] = eta;
     a.mn[o] = mnr;
-}
-
-// Fo, pass 1: mu_s = Mn phi0 cmu at the cells, and the relaxed history term
-// a_e So_e of every edge (a_e from the mean of the four cells' mu_s), once per
-// edge, into scratch.  Boundary edges carry zero.
-__global__ __launch_bounds__(AB) void k_fo_edges(Geom g, Coef c, RefreshCoef r, AuxPtrs a) {
-    Idx q;
-    if (!box_index(g, (int64_t)blockIdx.x * AB + threadIdx.x, q)) return;
-    const int i = q.i, j = q.j, k = q.k;
-    const int64_t o = at(g, i, j, k);
-    auto mus = [&](int ii, int jj, int kk) { return a.mn[at(g, ii, jj, kk)] * r.phi0 * r.cmu; };
-    if (i < g.nx && j < g.ny && k < g.nz) a.mus[o] = mus(i, j, k);
-    if (k < g.nz) {
-        double t = 0.0;
-        if (i >= 1 && i < g.nx && j >= 1 && j < g.ny) {
-            const double mue = 0.25 * (mus(i - 1, j - 1, k) + mus(i, j - 1, k) + mus(i - 1, j, k) + mus(i, j, k));
-            t = coef_a(mue, c.gdts_inv) * a.sxy[o];
-        }
-        a.scr0[o] = t;
-    }
-    if (j < g.ny) {
-        double t = 0.0;
-        if (i >= 1 && i < g.nx && k >= 1 && k < g.nz) {
-            const double mue = 0.25 * (mus(i - 1, j, k - 1) + mus(i, j, k - 1) + mus(i - 1, j, k) + mus(i, j, k));
-            t = coef_a(mue, c.gdts_inv) * a.sxz[o];
-        }
-        a.scr1[o] = t;
-    }
-    if (i < g.nx) {
-        double t = 0.0;
-        if (j >= 1 && j < g.ny && k >= 1 && k < g.nz) {
-            const double mue = 0.25 * (mus(i, j - 1, k - 1) + mus(i, j, k - 1) + mus(i, j - 1, k) + mus(i, j, k));
-            t = coef_a(mue, c.gdts_inv) * a.syz[o];
-        }
-        a.scr2[o] = t;
-    }
-}
-
-// Fo, pass 2: the stress-history part of the momentum balance folded into
-// face fields, Fo = div(a So) on interior faces (zero on boundary faces).
-__global__ __launch_bounds__(AB) void k_fo(Geom g, Coef c, AuxPtrs a) {
-    Idx q;
-    if (!box_index(g, (int64_t)blockIdx.x * AB + threadIdx.x, q)) return;
-    const int i = q.i, j = q.j, k = q.k;
-    const int64_t o = at(g, i, j, k);
-    auto acell = [&](int ii, int jj, int kk) { return coef_a(a.mus[at(g, ii, jj, kk)], c.gdts_inv); };
-    if (j < g.ny && k < g.nz) {  // x-face
-        double f = 0.0;
-        if (i >= 1 && i < g.nx)
-            f = (acell(i, j, k) * a.sxx[o] - acell(i - 1, j, k) * a.sxx[at(g, i - 1, j, k)]) * c.dxi +
-                (a.scr0[at(g, i, j + 1, k)] - a.scr0[o]) * c.dyi + (a.scr1[at(g, i, j, k + 1)] - a.scr1[o]) * c.dzi;
-        a.fox[o] = f;
-    }
-    if (i < g.nx && k < g.nz) {  // y-face
-        double f = 0.0;
-        if (j >= 1 && j < g.ny)
-            f = (a.scr0[at(g, i + 1, j, k)] - a.scr0[o]) * c.dxi +
-                (acell(i, j, k) * a.syy[o] - acell(i, j - 1, k) * a.syy[at(g, i, j - 1, k)]) * c.dyi +
-                (a.scr2[at(g, i, j, k + 1)] - a.scr2[o]) * c.dzi;
-        a.foy[o] = f;
-    }
-    if (i < g.nx && j < g.ny) {  // z-face
-        double f = 0.0;
-        if (k >= 1 && k < g.nz)
-            f = (a.scr1[at(g, i + 1, j, k)] - a.scr1[o]) * c.dxi + (a.scr2[at(g, i, j + 1, k)] - a.scr2[o]) * c.dyi +
-                (acell(i, j, k) * a.szz[o] - acell(i, j, k - 1) * a.szz[at(g, i, j, k - 1)]) * c.dzi;
-        a.foz[o] = f;
-    }
 }
 
 // Porosity time step of a Picard stage (eq (22)):
@@ -400,15 +298,13 @@ hipError_t launch_begin_step(const Geom& g, const Coef& c, const AuxPtrs& a, int
 }
 
 hipError_t launch_refresh(const Geom& g, const Coef& c, const RefreshCoef& r, const AuxPtrs& a, hipStream_t s) {
-    if (r.powerlaw || r.dpcap) hipLaunchKernelGGL(k_refresh_edges, box_grid(g), dim3(AB), 0, s, g, c, a);
+    if (r.powerlaw || r.dpcap) return launch_refresh_tiled(g, c, r, a, s);
     hipLaunchKernelGGL(k_refresh, box_grid(g), dim3(AB), 0, s, g, c, r, a);
     return hipGetLastError();
 }
 
 hipError_t launch_fo(const Geom& g, const Coef& c, const RefreshCoef& r, const AuxPtrs& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_fo_edges, box_grid(g), dim3(AB), 0, s, g, c, r, a);
-    hipLaunchKernelGGL(k_fo, box_grid(g), dim3(AB), 0, s, g, c, a);
-    return hipGetLastError();
+    return launch_fo_tiled(g, c, r, a, s);
 }
 
 hipError_t launch_porosity_step(const Geom& g, const Coef& c, const AuxPtrs& a, hipStream_t s) {

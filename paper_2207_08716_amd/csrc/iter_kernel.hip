@@ -81,15 +81,6 @@ struct CT {
           ab(T(c.ab)), third(T(c.third)), mech_off(c.mech_off) {}
 };
 
-// Tile order: consecutive tiles go to the same XCD (blocks are dealt to the
-// eight XCDs round robin), so tiles that share halo planes share an L2.
-__device__ __forceinline__ int64_t xcd_tile(int64_t L, int64_t total) {
-    const int64_t nx = 8;
-    int64_t xcd = L % nx, idx = L / nx;
-    int64_t q = total / nx, r = total % nx;
-    return (xcd < r) ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
-}
-
 template <typename T, int MODE, bool NORMS>
 __global__ __launch_bounds__((sweep_bx<MODE, NORMS>() * sweep_by<T, MODE, NORMS>())) void k_sweep(Geom g, Coef cd, SweepPtrs<T> p) {
     constexpr int W = sweep_bx<MODE, NORMS>();
@@ -111,26 +102,8 @@ __global__ __launch_bounds__((sweep_bx<MODE, NORMS>() * sweep_by<T, MODE, NORMS>
     const int by = (int)((Tt / gx) % gy);
     const int bz = (int)(Tt / ((int64_t)gx * gy));
 
-    // Thread layout.  In 66-wide blocks, wave r (r < H) takes the 64 interior
-    // columns of row r, so that every load and store of a row is one whole,
-    // aligned 512-byte segment; the last wave takes the two side halo columns
-    // of all rows.  64-wide blocks map lanes to columns directly.
     int tx, ty;
-    if constexpr (W == 64) {
-        tx = (int)threadIdx.x & 63;
-        ty = (int)threadIdx.x >> 6;
-    } else {
-        static_assert(W == 66, "sweep blocks are 64 or 66 wide");
-        const int L = threadIdx.x;
-        if (L < 64 * H) {
-            tx = 1 + (L & 63);
-            ty = L >> 6;
-        } else {
-            const int r = L - 64 * H;
-            tx = (r < H) ? 0 : W - 1;
-            ty = (r < H) ? r : r - H;
-        }
-    }
+    tile_thread<W, H>(tx, ty);
     const int i = bx * (W - 2) - 1 + tx;
     const int j = by * (H - 2) - 1 + ty;
     const int kz0 = bz * g.kz;
@@ -466,26 +439,29 @@ __global__ __launch_bounds__((sweep_bx<MODE, NORMS>() * sweep_by<T, MODE, NORMS>
     }
 
     if constexpr (WNORM) {
-        // block maximum: wave64 butterfly, then across the waves through LDS
-        static_assert((W * H) % 64 == 0, "norm variants need whole waves");
-        __shared__ double red[(W * H) / 64][NNORM];
+        // Block maximum: wave64 butterfly in each of the H row waves (the
+        // 66-wide layout's halo wave holds no tile cell and contributes
+        // nothing), then across the row waves through LDS.
+        __shared__ double red[H][NNORM];
+        const int L = threadIdx.x;
+        const int wave = L >> 6, lane = L & 63;
+        if (wave < H) {
 #pragma unroll
-        for (int q = 0; q < NNORM; ++q) {
-            T v = nm[q];
-            for (int off = 32; off >= 1; off >>= 1) v = nanmax(v, T(__shfl_xor(v, off, 64)));
-            nm[q] = v;
-        }
-        const int lin = ty * W + tx;
-        const int wave = lin >> 6, lane = lin & 63;
-        if (lane == 0) {
+            for (int q = 0; q < NNORM; ++q) {
+                T v = nm[q];
+                for (int off = 32; off >= 1; off >>= 1) v = nanmax(v, T(__shfl_xor(v, off, 64)));
+                nm[q] = v;
+            }
+            if (lane == 0) {
 #pragma unroll
-            for (int q = 0; q < NNORM; ++q) red[wave][q] = double(nm[q]);
+                for (int q = 0; q < NNORM; ++q) red[wave][q] = double(nm[q]);
+            }
         }
         __syncthreads();
-        if (lin < NNORM) {
+        if (L < NNORM) {
             double v = 0.0;
-            for (int wv = 0; wv < (W * H) / 64; ++wv) v = nanmax(v, red[wv][lin]);
-            p.partials[(int64_t)blockIdx.x * NNORM + lin] = v;
+            for (int wv = 0; wv < H; ++wv) v = nanmax(v, red[wv][L]);
+            p.partials[(int64_t)blockIdx.x * NNORM + L] = v;
         }
     }
 }

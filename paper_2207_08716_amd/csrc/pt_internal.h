@@ -116,6 +116,40 @@ inline int64_t iter_grid_blocks(const Geom& g, int bx, int by) {
     return tiles_xy(v, bx, by) * ((v.nz + v.kz - 1) / v.kz);
 }
 
+// Tile order of the z-marching kernels: consecutive tiles go to the same XCD
+// (blocks are dealt to the eight XCDs round robin), so tiles that share halo
+// planes share an L2.
+__device__ __forceinline__ int64_t xcd_tile(int64_t L, int64_t total) {
+    const int64_t nx = 8;
+    int64_t xcd = L % nx, idx = L / nx;
+    int64_t q = total / nx, r = total % nx;
+    return (xcd < r) ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
+}
+
+// Thread layout of a W x H tile block (one-dimensional launch of W*H
+// threads).  In 66-wide blocks wave r (r < H) takes the 64 interior columns
+// of row r, so that every load and store of a row is one whole, aligned
+// 512-byte segment, and the last wave takes the two side halo columns of all
+// rows.  64-wide blocks map lanes to columns directly.
+template <int W, int H>
+__device__ __forceinline__ void tile_thread(int& tx, int& ty) {
+    if constexpr (W == 64) {
+        tx = (int)threadIdx.x & 63;
+        ty = (int)threadIdx.x >> 6;
+    } else {
+        static_assert(W == 66, "tile blocks are 64 or 66 wide");
+        const int L = threadIdx.x;
+        if (L < 64 * H) {
+            tx = 1 + (L & 63);
+            ty = L >> 6;
+        } else {
+            const int r = L - 64 * H;
+            tx = (r < H) ? 0 : W - 1;
+            ty = (r < H) ? r : r - H;
+        }
+    }
+}
+
 // Blocks that write per-block norm maxima (size of the partials area).
 inline int64_t norm_blocks(const Geom& g) { return iter_grid_blocks(g, BX_NORMS, BY_NORMS); }
 
@@ -137,7 +171,6 @@ struct AuxPtrs {
     double *mn, *kc, *eta, *mus;
     const double* k0;
     double* lp_o;                  // porosity step output
-    double *scr0, *scr1, *scr2;    // three padded-box scratch fields (workspace)
 };
 
 struct RefreshCoef {
@@ -151,6 +184,9 @@ hipError_t launch_begin_step(const Geom& g, const Coef& c, const AuxPtrs& a, int
                              hipStream_t s);
 hipError_t launch_refresh(const Geom& g, const Coef& c, const RefreshCoef& r, const AuxPtrs& a,
                           hipStream_t s);
+hipError_t launch_refresh_tiled(const Geom& g, const Coef& c, const RefreshCoef& r, const AuxPtrs& a,
+                                hipStream_t s);
+hipError_t launch_fo_tiled(const Geom& g, const Coef& c, const RefreshCoef& r, const AuxPtrs& a, hipStream_t s);
 hipError_t launch_fo(const Geom& g, const Coef& c, const RefreshCoef& r, const AuxPtrs& a,
                      hipStream_t s);
 hipError_t launch_porosity_step(const Geom& g, const Coef& c, const AuxPtrs& a, hipStream_t s);
