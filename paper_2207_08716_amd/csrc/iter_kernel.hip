@@ -42,10 +42,11 @@ struct Lds {
 };
 
 // Block width of a sweep variant: the plain sweeps use BX (64-column output
-// tiles), the variants that also reduce norms BX_NORMS (whole waves for the
-// shuffle reduction, and 8 waves, which leaves them 256 registers).
-template <int MODE, bool NORMS>
+// tiles); the FP64 variants that also reduce norms BX_NORMS (8 whole waves,
+// which leaves them the 256 registers they need), the FP32 one BX_NORMS32.
+template <typename T, int MODE, bool NORMS>
 constexpr int sweep_bx() {
+    if (NORMS && MODE == MD_CORR && sizeof(T) == 4) return BX_NORMS32;
     return (NORMS || MODE == MD_RESID) ? BX_NORMS : BX;
 }
 // Block height: taller tiles re-read fewer halo rows but need registers for
@@ -54,6 +55,7 @@ constexpr int sweep_bx() {
 // and were measured fastest at 511^3.
 template <typename T, int MODE, bool NORMS>
 constexpr int sweep_by() {
+    if (NORMS && MODE == MD_CORR && sizeof(T) == 4) return BY_NORMS32;
     if (NORMS || MODE == MD_RESID) return BY_NORMS;
     if (MODE == MD_THESIS) return BY;
     if (MODE == MD_CORR && sizeof(T) == 4) return BY_CORR32;
@@ -82,8 +84,8 @@ struct CT {
 };
 
 template <typename T, int MODE, bool NORMS>
-__global__ __launch_bounds__((sweep_bx<MODE, NORMS>() * sweep_by<T, MODE, NORMS>())) void k_sweep(Geom g, Coef cd, SweepPtrs<T> p) {
-    constexpr int W = sweep_bx<MODE, NORMS>();
+__global__ __launch_bounds__((sweep_bx<T, MODE, NORMS>() * sweep_by<T, MODE, NORMS>())) void k_sweep(Geom g, Coef cd, SweepPtrs<T> p) {
+    constexpr int W = sweep_bx<T, MODE, NORMS>();
     constexpr int H = sweep_by<T, MODE, NORMS>();
     static_assert(W * H <= 1024, "a block holds at most 1024 threads");
     constexpr bool UPD_LP = (MODE == MD_THESIS);
@@ -499,7 +501,7 @@ __global__ __launch_bounds__(256) void k_reduce_max(const double* __restrict__ p
 
 template <typename T, int MODE, bool NORMS>
 void launch_sweep(const Geom& g, const Coef& c, const SweepPtrs<T>& p, hipStream_t s) {
-    constexpr int W = sweep_bx<MODE, NORMS>(), H = sweep_by<T, MODE, NORMS>();
+    constexpr int W = sweep_bx<T, MODE, NORMS>(), H = sweep_by<T, MODE, NORMS>();
     const Geom v = sweep_geom(g, W, H);
     hipLaunchKernelGGL((k_sweep<T, MODE, NORMS>), dim3((unsigned)iter_grid_blocks(g, W, H)), dim3(W * H, 1, 1), 0, s,
                        v, c, p);

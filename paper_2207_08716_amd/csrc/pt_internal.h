@@ -74,8 +74,10 @@ constexpr int BX = 66;
 constexpr int BY = 10;         // thesis sweep
 constexpr int BY_LINEAR = 10;  // linear and FP64 correction sweeps
 constexpr int BY_CORR32 = 14;  // FP32 correction sweep
-constexpr int BX_NORMS = 64;
+constexpr int BX_NORMS = 64;     // FP64 sweeps with norms (195 VGPRs: 8 waves)
 constexpr int BY_NORMS = 8;
+constexpr int BX_NORMS32 = 66;   // FP32 correction sweep with norms (102 VGPRs)
+constexpr int BY_NORMS32 = 7;
 constexpr int KZ_MAX = 64;
 
 constexpr int KZ_MIN = 4;
@@ -151,7 +153,9 @@ __device__ __forceinline__ void tile_thread(int& tx, int& ty) {
 }
 
 // Blocks that write per-block norm maxima (size of the partials area).
-inline int64_t norm_blocks(const Geom& g) { return iter_grid_blocks(g, BX_NORMS, BY_NORMS); }
+inline int64_t norm_blocks(const Geom& g) { return iter_grid_blocks(g, BX_NORMS, BY_NORMS); }    // FP64
+inline int64_t norm_blocks32(const Geom& g) { return iter_grid_blocks(g, BX_NORMS32, BY_NORMS32); }
+inline int64_t norm_area(const Geom& g) { return std::max(norm_blocks(g), norm_blocks32(g)); }
 
 // Launchers (defined in the .hip files).
 hipError_t launch_iteration(const Geom& g, const Coef& c, const SweepPtrs<double>& p, int mode,
