@@ -139,18 +139,24 @@ __global__ __launch_bounds__((sweep_bx<T, MODE, NORMS>() * sweep_by<T, MODE, NOR
         q.lp = CORR ? zero : p.lp[o];
     };
     // The cell set is loaded only by the threads that use it (halo columns
-    // would otherwise fetch tile-only fields from HBM a second time).
+    // would otherwise fetch tile-only fields from HBM a second time).  The
+    // tile-only fields are read exactly once per launch: non-temporal loads
+    // keep them from displacing halo data in the caches.
     auto load_c = [&](int k, CSet& cs) {
         const int64_t o = at(k);
         if (cellq) {
             cs.pt = p.pt[o]; cs.pto = p.pto[o]; cs.pfo = p.pfo[o]; cs.eta = p.eta[o];
         }
         if (outc) {
-            cs.lpo = UPD_LP ? p.lpo[o] : zero;
+            cs.lpo = UPD_LP ? __builtin_nontemporal_load(&p.lpo[o]) : zero;
             if (!RESID) {
-                cs.rx = p.rx[o]; cs.ry = p.ry[o]; cs.rz = p.rz[o];
+                cs.rx = __builtin_nontemporal_load(&p.rx[o]);
+                cs.ry = __builtin_nontemporal_load(&p.ry[o]);
+                cs.rz = __builtin_nontemporal_load(&p.rz[o]);
             }
-            cs.fox = p.fox[o]; cs.foy = p.foy[o]; cs.foz = p.foz[o];
+            cs.fox = __builtin_nontemporal_load(&p.fox[o]);
+            cs.foy = __builtin_nontemporal_load(&p.foy[o]);
+            cs.foz = __builtin_nontemporal_load(&p.foz[o]);
         }
     };
     auto mask_q = [&](int k, QSet& q) {

@@ -78,7 +78,7 @@ constexpr int BX_NORMS = 64;     // FP64 sweeps with norms (195 VGPRs: 8 waves)
 constexpr int BY_NORMS = 8;
 constexpr int BX_NORMS32 = 66;   // FP32 correction sweep with norms (102 VGPRs)
 constexpr int BY_NORMS32 = 7;
-constexpr int KZ_MAX = 64;
+constexpr int KZ_MAX = 256;
 
 constexpr int KZ_MIN = 4;
 constexpr int64_t GPU_CUS = 256;   // MI355X compute units (one sweep block each)
