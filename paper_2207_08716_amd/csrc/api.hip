@@ -173,10 +173,9 @@ pt_status check_ready(pt_grid* g) {
 }
 
 // Workspace layout (doubles): [partials: n_blocks * 8][norms: 8], padded to
-// a multiple of 256 bytes; n_blocks is the larger block count of the two
-// norm tilings (FP64 and FP32 sweeps), and the norms sit after that area.
+// a multiple of 256 bytes.
 size_t ws_needed(const pt_grid* g) {
-    const int64_t head = norm_area(g->geom) * NNORM + NNORM;
+    const int64_t head = norm_blocks(g->geom) * NNORM + NNORM;
     return (size_t)((head + 31) / 32 * 32) * sizeof(double);
 }
 
@@ -206,11 +205,9 @@ SweepPtrs<double> sweep_ptrs(pt_grid* g) {
     return p;
 }
 
-// Reduce the partial maxima of the nb blocks of the last norm-writing launch
-// (norm_blocks for the FP64 sweeps and the norm helpers, norm_blocks32 for
-// the FP32 correction sweep).
-pt_status reduce_norms(pt_grid* g, int64_t nb) {
-    double* out = static_cast<double*>(g->ws) + norm_area(g->geom) * NNORM;
+pt_status reduce_norms(pt_grid* g) {
+    const int64_t nb = norm_blocks(g->geom);
+    double* out = static_cast<double*>(g->ws) + nb * NNORM;
     hipError_t e = launch_reduce_max(static_cast<double*>(g->ws), nb, out, g->stream);
     if (e != hipSuccess) return hip_fail(g, e, "reduce");
     g->norms_pending = true;
@@ -222,7 +219,7 @@ pt_status iteration_impl(pt_grid* g, int update_lp, int norms) {
     hipError_t e = launch_iteration(g->geom, g->coef, p, update_lp ? MD_THESIS : MD_LINEAR, norms, g->stream);
     if (e != hipSuccess) return hip_fail(g, e, "iteration");
     if (norms) {
-        pt_status st = reduce_norms(g, norm_blocks(g->geom));
+        pt_status st = reduce_norms(g);
         if (st != PT_OK) return st;
     }
     for (int f = 0; f < PT_NPING; ++f) {
@@ -246,7 +243,7 @@ float* mx(pt_grid* g, int b) { return g->mws + (int64_t)b * mx_box(g); }
 
 pt_status read_norms(pt_grid* g, pt_norms* out) {
     double host[NNORM];
-    hipError_t e = hipMemcpyAsync(host, static_cast<double*>(g->ws) + norm_area(g->geom) * NNORM, sizeof(host),
+    hipError_t e = hipMemcpyAsync(host, static_cast<double*>(g->ws) + norm_blocks(g->geom) * NNORM, sizeof(host),
                                   hipMemcpyDeviceToHost, g->stream);
     if (e != hipSuccess) return hip_fail(g, e, "norms copy");
     e = hipStreamSynchronize(g->stream);
@@ -512,7 +509,7 @@ pt_status pt_residual(pt_grid* g) {
     p.res_rpf = mx(g, MX_RES + 4);
     hipError_t e = launch_iteration(g->geom, g->coef, p, MD_RESID, 1, g->stream);
     if (e != hipSuccess) return hip_fail(g, e, "residual");
-    return reduce_norms(g, norm_blocks(g->geom));
+    return reduce_norms(g);
 }
 
 namespace {
@@ -532,7 +529,7 @@ pt_status correction_sweep(pt_grid* g, int cp, int norms) {
     p.partials = static_cast<double*>(g->ws);
     hipError_t e = launch_correction(g->geom, g->coef, p, norms, g->stream);
     if (e != hipSuccess) return hip_fail(g, e, "correction sweep");
-    if (norms) return reduce_norms(g, norm_blocks32(g->geom));
+    if (norms) return reduce_norms(g);
     return PT_OK;
 }
 
@@ -608,7 +605,7 @@ pt_status mixed_core(pt_grid* g, const MixedTarget& t, double rtol, double eta_i
     for (;;) {
         e = launch_iteration(g->geom, t.coef, rp, MD_RESID, 1, g->stream);
         if (e != hipSuccess) return hip_fail(g, e, "residual");
-        st = reduce_norms(g, norm_blocks(g->geom));
+        st = reduce_norms(g);
         if (st != PT_OK) return st;
         pt_norms nm;
         st = read_norms(g, &nm);
@@ -772,7 +769,7 @@ pt_status transposed_solve(pt_grid* g, const double* kc, const double* mus, doub
     const double* rhs[5] = {ad(g, AD_RHS), ad(g, AD_RHS + 1), ad(g, AD_RHS + 2), ad(g, AD_RHS + 3), ad(g, AD_RHS + 4)};
     e = launch_absmax5(g->geom, rhs, static_cast<double*>(g->ws), nb, g->stream);
     if (e != hipSuccess) return hip_fail(g, e, "rhs norm");
-    pt_status st = reduce_norms(g, norm_blocks(g->geom));
+    pt_status st = reduce_norms(g);
     if (st != PT_OK) return st;
     pt_norms n0;
     st = read_norms(g, &n0);
@@ -803,7 +800,7 @@ pt_status transposed_solve(pt_grid* g, const double* kc, const double* mus, doub
             if (e != hipSuccess) return hip_fail(g, e, "adjoint sweep");
             cp ^= 1;
             if (chk) {
-                st = reduce_norms(g, norm_blocks(g->geom));
+                st = reduce_norms(g);
                 if (st != PT_OK) return st;
                 pt_norms nm;
                 st = read_norms(g, &nm);

@@ -41,12 +41,10 @@ struct Lds {
     T txz[2][H][W], tyz[2][H][W];
 };
 
-// Block width of a sweep variant: the plain sweeps use BX (64-column output
-// tiles); the FP64 variants that also reduce norms BX_NORMS (8 whole waves,
-// which leaves them the 256 registers they need), the FP32 one BX_NORMS32.
+// Block width of a sweep variant: the plain sweeps use BX, the variants that
+// also reduce norms BX_NORMS (both give 64-column output tiles).
 template <typename T, int MODE, bool NORMS>
 constexpr int sweep_bx() {
-    if (NORMS && MODE == MD_CORR && sizeof(T) == 4) return BX_NORMS32;
     return (NORMS || MODE == MD_RESID) ? BX_NORMS : BX;
 }
 // Block height: taller tiles re-read fewer halo rows but need registers for
@@ -55,7 +53,6 @@ constexpr int sweep_bx() {
 // and were measured fastest at 511^3.
 template <typename T, int MODE, bool NORMS>
 constexpr int sweep_by() {
-    if (NORMS && MODE == MD_CORR && sizeof(T) == 4) return BY_NORMS32;
     if (NORMS || MODE == MD_RESID) return BY_NORMS;
     if (MODE == MD_THESIS) return BY;
     if (MODE == MD_CORR && sizeof(T) == 4) return BY_CORR32;

@@ -65,8 +65,9 @@ constexpr int NNORM = 8;
 // boundaries of the padded rows (whole cache lines written) and n = 2^k - 1
 // grids fill their last tile; each row's 64 interior columns are one wave,
 // the side halo columns of all rows one more (partial) wave.  The variants
-// that also reduce norms use BX_NORMS = 64 (whole waves).  Every cell's
-// arithmetic is the same in both tilings.  Heights: the tallest tile whose
+// that also reduce norms need up to 196 registers, so at most 8 waves: 7
+// rows.  Every cell's arithmetic is the same in every tiling.  Heights: the
+// tallest tile whose
 // waves fit the variant's registers is not always the fastest, since the
 // number of tiles decides how full the last round of blocks is; measured
 // at 511^3 (8-row tiles: 86 tile rows, 10-row tiles: 64).
@@ -74,10 +75,8 @@ constexpr int BX = 66;
 constexpr int BY = 10;         // thesis sweep
 constexpr int BY_LINEAR = 10;  // linear and FP64 correction sweeps
 constexpr int BY_CORR32 = 14;  // FP32 correction sweep
-constexpr int BX_NORMS = 64;     // FP64 sweeps with norms (195 VGPRs: 8 waves)
-constexpr int BY_NORMS = 8;
-constexpr int BX_NORMS32 = 66;   // FP32 correction sweep with norms (102 VGPRs)
-constexpr int BY_NORMS32 = 7;
+constexpr int BX_NORMS = 66;     // sweeps with norms (up to 196 VGPRs: 8 waves)
+constexpr int BY_NORMS = 7;
 constexpr int KZ_MAX = 256;
 
 constexpr int KZ_MIN = 4;
@@ -153,9 +152,7 @@ __device__ __forceinline__ void tile_thread(int& tx, int& ty) {
 }
 
 // Blocks that write per-block norm maxima (size of the partials area).
-inline int64_t norm_blocks(const Geom& g) { return iter_grid_blocks(g, BX_NORMS, BY_NORMS); }    // FP64
-inline int64_t norm_blocks32(const Geom& g) { return iter_grid_blocks(g, BX_NORMS32, BY_NORMS32); }
-inline int64_t norm_area(const Geom& g) { return std::max(norm_blocks(g), norm_blocks32(g)); }
+inline int64_t norm_blocks(const Geom& g) { return iter_grid_blocks(g, BX_NORMS, BY_NORMS); }
 
 // Launchers (defined in the .hip files).
 hipError_t launch_iteration(const Geom& g, const Coef& c, const SweepPtrs<double>& p, int mode,
