@@ -227,10 +227,10 @@ def test_parity_ragged_linear_and_correction_sweeps(shape):
 
 
 def test_tilings_give_bitwise_equal_fields():
-    """The sweeps with norms run on 64x8 blocks, the plain ones on 66x10
-    blocks with another thread layout: every cell's arithmetic is the same, so a run
-    that takes the norms at every iteration equals, bit for bit, one that
-    never does (thesis and linear sweeps, ragged grid)."""
+    """The sweeps with norms run on 66x7 blocks, the plain ones on 66x10
+    blocks (other tile rows, other z chunks): every cell's arithmetic is the
+    same, so a run that takes the norms at every iteration equals, bit for
+    bit, one that never does (thesis and linear sweeps, ragged grid)."""
     import dataclasses
     cfg = inputs.config_fp64_picard(8)
     cfg = dataclasses.replace(cfg, nx=70, ny=23, nz=19, name="tilings")
