@@ -80,10 +80,12 @@ struct CT {
           ab(T(c.ab)), third(T(c.third)), mech_off(c.mech_off) {}
 };
 
-template <typename T, int MODE, bool NORMS>
-__global__ __launch_bounds__((sweep_bx<T, MODE, NORMS>() * sweep_by<T, MODE, NORMS>())) void k_sweep(Geom g, Coef cd, SweepPtrs<T> p) {
+// HV, if not 0, overrides the variant's block height.
+template <typename T, int MODE, bool NORMS, int HV = 0>
+__global__ __launch_bounds__((sweep_bx<T, MODE, NORMS>() * (HV ? HV : sweep_by<T, MODE, NORMS>()))) void k_sweep(
+    Geom g, Coef cd, SweepPtrs<T> p) {
     constexpr int W = sweep_bx<T, MODE, NORMS>();
-    constexpr int H = sweep_by<T, MODE, NORMS>();
+    constexpr int H = HV ? HV : sweep_by<T, MODE, NORMS>();
     static_assert(W * H <= 1024, "a block holds at most 1024 threads");
     constexpr bool UPD_LP = (MODE == MD_THESIS);
     constexpr bool RESID = (MODE == MD_RESID);
@@ -509,12 +511,12 @@ __global__ __launch_bounds__(256) void k_reduce_max(const double* __restrict__ p
 
 }  // namespace
 
-template <typename T, int MODE, bool NORMS>
+template <typename T, int MODE, bool NORMS, int HV = 0>
 void launch_sweep(const Geom& g, const Coef& c, const SweepPtrs<T>& p, hipStream_t s) {
-    constexpr int W = sweep_bx<T, MODE, NORMS>(), H = sweep_by<T, MODE, NORMS>();
+    constexpr int W = sweep_bx<T, MODE, NORMS>(), H = HV ? HV : sweep_by<T, MODE, NORMS>();
     const Geom v = sweep_geom(g, W, H);
-    hipLaunchKernelGGL((k_sweep<T, MODE, NORMS>), dim3((unsigned)iter_grid_blocks(g, W, H)), dim3(W * H, 1, 1), 0, s,
-                       v, c, p);
+    hipLaunchKernelGGL((k_sweep<T, MODE, NORMS, HV>), dim3((unsigned)iter_grid_blocks(g, W, H)), dim3(W * H, 1, 1), 0,
+                       s, v, c, p);
 }
 
 hipError_t launch_iteration(const Geom& g, const Coef& c, const SweepPtrs<double>& p, int mode, int norms,
@@ -539,6 +541,7 @@ hipError_t launch_iteration(const Geom& g, const Coef& c, const SweepPtrs<double
 
 hipError_t launch_correction(const Geom& g, const Coef& c, const SweepPtrs<float>& p, int norms, hipStream_t s) {
     if (norms) launch_sweep<float, MD_CORR, true>(g, c, p, s);
+    else if (corr32_short(g)) launch_sweep<float, MD_CORR, false, BY_CORR32_SHORT>(g, c, p, s);
     else launch_sweep<float, MD_CORR, false>(g, c, p, s);
     return hipGetLastError();
 }

@@ -19,7 +19,7 @@ from collections import defaultdict
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 KERNEL_SRC = os.path.join(ROOT, "paper_2207_08716_amd", "csrc", "iter_kernel.hip")
-DOMINANT = "k_sweep<double, 0, false>"
+DOMINANT = "k_sweep<double, 0, false"   # thesis sweep without norms
 COPY = "k_copy"
 
 
