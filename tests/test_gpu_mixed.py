@@ -87,3 +87,46 @@ def test_mixed_picard_step_matches_oracle():
     for name in FIELDS + ("lp", "kc", "eta", "mus"):
         r = _rel(g.get(name), o.f[name])
         assert r <= 1e-5, (name, r)
+
+
+def _fp32_tall_tiles(nx, ny, nz):
+    """Whether the launch cost model of the library puts the FP32 correction
+    sweep on its 14-row tiles (rather than 10-row ones) for this grid: the
+    best z chunk's rounds of 256 blocks times (chunk + 2) times the rows."""
+    def cost(by):
+        tiles = ((nx + 63) // 64) * ((ny + by - 3) // (by - 2))
+        best, kz = None, 256
+        while kz >= 4:
+            blocks = tiles * ((nz + kz - 1) // kz)
+            c = ((blocks + 255) // 256) * (min(kz, nz) + 2)
+            best = c if best is None or c < best else best
+            kz //= 2
+        return best * by
+    return cost(14) < cost(10)
+
+
+def test_mixed_stage_on_tall_fp32_tiles():
+    """192x84x32: the only kind of grid in these tests where the FP32
+    correction sweep runs 14-row tiles (the small grids all take 10-row
+    ones).  A converged mixed stage matches the FP64 stage, itself checked
+    against the oracle elsewhere, within 1e-5 per field."""
+    import dataclasses
+    nx, ny, nz = 192, 84, 32
+    assert _fp32_tall_tiles(nx, ny, nz) and not _fp32_tall_tiles(24, 24, 24)
+    cfg = inputs.config_mixed(8)
+    cfg = dataclasses.replace(cfg, nx=nx, ny=ny, nz=nz, name="tall-fp32")
+    cfg.phys = cfg.phys.replace(lx=nx / 64, ly=ny / 64, lz=nz / 64)
+    f = inputs.initial_fields(cfg)
+    g64 = _grid(cfg, f)
+    g64.begin_step(False)
+    g64.refresh(1.0, 1.0)
+    it64, rho64, ok64 = g64.solve_linear(1e-10, 400000)
+    gmx = _grid(cfg, f)
+    gmx.begin_step(False)
+    gmx.refresh(1.0, 1.0)
+    inner, outer, rhomx, okmx = gmx.solve_mixed(1e-10, 1e-4, 400000, 60)
+    print("fp64", it64, rho64, "mixed", inner, outer, rhomx, flush=True)
+    assert ok64 and okmx and outer >= 2
+    worst = {name: _rel(gmx.get(name), g64.get(name)) for name in FIELDS}
+    print(worst, flush=True)
+    assert max(worst.values()) <= 1e-5, worst
