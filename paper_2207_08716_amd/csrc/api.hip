@@ -732,19 +732,29 @@ pt_status sensor_offsets(pt_grid* g, const int64_t* sensors, int32_t ns, std::ve
     return PT_OK;
 }
 
+// Small host-to-device copy from caller-side or temporary host memory: the
+// stream is synchronised before returning, so the source may be freed at once
+// (also on error paths).
+static hipError_t upload_sync(void* dst, const void* src, size_t bytes, hipStream_t s) {
+    hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);
+    const hipError_t e2 = hipStreamSynchronize(s);
+    return e != hipSuccess ? e : e2;
+}
+
 // J = 1/2 sum (Pf_s - d_s)^2 of the present state; leaves the gathered Pf in vals.
 pt_status misfit_impl(pt_grid* g, const int64_t* sensors, int32_t ns, const double* d_obs, double* J,
                       std::vector<double>& resid) {
     std::vector<int64_t> offs;
     pt_status st = sensor_offsets(g, sensors, ns, offs);
     if (st != PT_OK) return st;
-    hipError_t e = hipMemcpyAsync(ad_offs(g), offs.data(), ns * sizeof(int64_t), hipMemcpyHostToDevice, g->stream);
+    hipError_t e = upload_sync(ad_offs(g), offs.data(), ns * sizeof(int64_t), g->stream);
     if (e != hipSuccess) return hip_fail(g, e, "sensor upload");
     e = launch_gather(cur(g, PT_PF), ad_offs(g), ns, ad_vals(g), g->stream);
     if (e != hipSuccess) return hip_fail(g, e, "gather");
     std::vector<double> vals(ns);
     e = hipMemcpyAsync(vals.data(), ad_vals(g), ns * sizeof(double), hipMemcpyDeviceToHost, g->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(g->stream);
+    const hipError_t es = hipStreamSynchronize(g->stream);   // also on a failed copy: vals is local
+    if (e == hipSuccess) e = es;
     if (e != hipSuccess) return hip_fail(g, e, "gather download");
     resid.resize(ns);
     double acc = 0.0;
@@ -934,7 +944,7 @@ pt_status pt_adjoint_stage(pt_grid* g, const int64_t* sensors, int32_t ns, const
     for (int32_t s = 0; s < ns; ++s) seed[s] = -resid[s];   // -xbar, xbar = dJ/dPf
     const int64_t box_bytes = mx_box(g) * (int64_t)sizeof(double);
     hipError_t e = hipMemsetAsync(ad(g, AD_RHS), 0, 5 * box_bytes, g->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(ad_seed(g), seed.data(), ns * sizeof(double), hipMemcpyHostToDevice, g->stream);
+    if (e == hipSuccess) e = upload_sync(ad_seed(g), seed.data(), ns * sizeof(double), g->stream);
     if (e == hipSuccess) e = launch_scatter(ad_seed(g), ad_offs(g), ns, ad(g, AD_RHS + 4), g->stream);
     if (e == hipSuccess) e = launch_chi64(g->geom, cur(g, PT_ETA), cur(g, PT_LP), ad(g, AD_CHI), g->stream);
     if (e != hipSuccess) return hip_fail(g, e, "adjoint set-up");
@@ -1100,7 +1110,7 @@ pt_status pt_adjoint_run(pt_grid* g, int32_t n_steps, int32_t n_picard, int32_t 
     if (e == hipSuccess) e = hipMemsetAsync(grad_dev, 0, box_bytes, g->stream);
     std::vector<double> seed(ns);
     for (int32_t s = 0; s < ns; ++s) seed[s] = -resid[s];
-    if (e == hipSuccess) e = hipMemcpyAsync(ad_seed(g), seed.data(), ns * sizeof(double), hipMemcpyHostToDevice, g->stream);
+    if (e == hipSuccess) e = upload_sync(ad_seed(g), seed.data(), ns * sizeof(double), g->stream);
     if (e == hipSuccess) e = launch_scatter(ad_seed(g), ad_offs(g), ns, ad(g, AD_RHS + 4), g->stream);
     if (e != hipSuccess) return hip_fail(g, e, "run adjoint set-up");
     AdjPtrs a{};
