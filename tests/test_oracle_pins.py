@@ -450,6 +450,47 @@ def test_power_law_viscosity_limits():
     del mn_old
 
 
+def test_stress_invariant_closed_forms():
+    """tau_II of eq (21)'s stresses (without the numerical compressibility
+    term), as the refresh uses it, for fields whose invariant is known in
+    closed form, with uniform mu_s (b = 2 mu/(1+xi), a = xi/(1+xi)):
+    pure shear V = (e x, -e y, 0): tau_xx = b e = -tau_yy, tau_II = b e;
+    simple shear V = (g y, 0, 0): tau_xy = b g/2 on interior edges, so
+    tau_II = b g/2 in cells whose four xy-edges are interior;
+    history only (V = 0): So_xx = s = -So_yy gives tau_II = a s, and a uniform
+    So_xy = t on interior edges gives a t in the inner cells."""
+    cfg = inputs.config_parity(8)
+    ph = cfg.phys
+    n = 8
+    f = inputs.initial_fields(cfg)
+    dx, dy = ph.lx / n, ph.ly / n
+    mu = ph.mu0 * ph.phi0 * ph.cmu
+    xi = mu / (ph.G * ph.dtS)
+    b, a = 2.0 * mu / (1.0 + xi), xi / (1.0 + xi)
+    inner = (slice(None), slice(1, n - 1), slice(1, n - 1))
+
+    o = oracle.Oracle(ph, n, n, n, f["phi"], None)
+    e = 0.3
+    o.f["vx"][...] = e * (np.arange(n + 1) * dx)[None, None, :]
+    o.f["vy"][...] = -e * (np.arange(n + 1) * dy)[None, :, None]
+    assert np.allclose(o.tau_ii(), b * e, rtol=1e-13, atol=0)
+
+    o = oracle.Oracle(ph, n, n, n, f["phi"], None)
+    g = 0.7
+    o.f["vx"][...] = g * ((np.arange(n) + 0.5) * dy)[None, :, None]
+    assert np.allclose(o.tau_ii()[inner], 0.5 * b * g, rtol=1e-13, atol=0)
+
+    o = oracle.Oracle(ph, n, n, n, f["phi"], None)
+    s_, t_ = 0.2, 0.05
+    o.f["sxx"][...] = s_
+    o.f["syy"][...] = -s_
+    assert np.allclose(o.tau_ii(), a * s_, rtol=1e-13, atol=0)
+    o.f["sxx"][...] = 0.0
+    o.f["syy"][...] = 0.0
+    o.f["sxy"][...] = t_
+    assert np.allclose(o.tau_ii()[inner], a * t_, rtol=1e-13, atol=0)
+
+
 # ---------------------------------------------------------------------------
 # 9. Seeded inputs are reproducible and have the stated statistics
 # ---------------------------------------------------------------------------
