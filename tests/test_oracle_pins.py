@@ -450,6 +450,25 @@ def test_power_law_viscosity_limits():
     del mn_old
 
 
+def test_log_space_relaxation_of_the_refresh():
+    """After the first refresh of a run, eta_phi and Mn relax in log space:
+    x = x_new^r x_old^(1-r).  At phi = phi0, Pf <= Pt and no stress
+    dependence, eta_new = eta0 Mn_old and Mn_new = mu0, so from chosen old
+    values the relaxed ones follow in closed form (r = 0.5, 0.1 and 1)."""
+    n = 4
+    ph = inputs.Physics()
+    for r_eta, r_mu in ((0.5, 0.1), (1.0, 1.0), (0.25, 0.75)):
+        o = make(ph, n)                       # phi = phi0 everywhere
+        o.refresh()                           # the first refresh takes new values
+        eta_old, mn_old = 4.0, 0.25
+        o.f["eta"][...] = eta_old
+        o.f["mn"][...] = mn_old
+        o.refresh(r_eta=r_eta, r_mu=r_mu)
+        eta_new = ph.eta0 * mn_old
+        assert np.allclose(o.f["eta"], eta_new ** r_eta * eta_old ** (1 - r_eta), rtol=1e-14, atol=0)
+        assert np.allclose(o.f["mn"], ph.mu0 ** r_mu * mn_old ** (1 - r_mu), rtol=1e-14, atol=0)
+
+
 def test_stress_invariant_closed_forms():
     """tau_II of eq (21)'s stresses (without the numerical compressibility
     term), as the refresh uses it, for fields whose invariant is known in
