@@ -34,6 +34,16 @@ SRC_PATH = os.path.join(_HERE, "oracle.c")
 
 NORM_NAMES = ("f", "rpt", "rpf", "dL", "dPt", "dPf", "dVz", "dV")
 
+# Alternative readings of the iteration (oracle.c OR_V_*); 0 = the readings
+# the solver implements.  They change the pseudo-time path, not the solution.
+V_BETAN_UPDATED = 1   # beta_n r_Pt in the stresses taken at the updated Pt'
+V_DTV_PRINTED = 2     # velocity pseudo-step with (1+beta_n) as printed
+V_DTPF_CELL = 4       # fluid-pressure pseudo-step from the cell's own k/mu_f
+
+
+class OracleDiverged(FloatingPointError):
+    """A residual norm of the oracle is not finite."""
+
 
 def build(force: bool = True) -> str:
     """Compile oracle.c into liboracle.so (gcc, -O2, no FMA contraction)."""
@@ -60,7 +70,8 @@ class _Params(C.Structure):
                 ("damp_c", C.c_double),
                 ("powerlaw", C.c_int32), ("dpcap", C.c_int32), ("mech_off", C.c_int32),
                 ("k0field", C.c_int32), ("ngx", C.c_int32), ("ngy", C.c_int32), ("ngz", C.c_int32),
-                ("hx", C.c_double), ("hy", C.c_double), ("hz", C.c_double)]
+                ("hx", C.c_double), ("hy", C.c_double), ("hz", C.c_double),
+                ("variant", C.c_int32)]
 
 
 _STATE_FIELDS = ("vx", "vy", "vz", "pt", "pf", "lp", "rx", "ry", "rz", "pto", "pfo",
@@ -129,16 +140,17 @@ class Oracle:
     phi:  initial porosity, (nz, ny, nx).  k0: per-cell k0/mu_f or None.
     """
 
-    def __init__(self, phys, nx, ny, nz, phi, k0=None, global_counts=None):
+    def __init__(self, phys, nx, ny, nz, phi, k0=None, global_counts=None, variant=0):
         """global_counts: (nx, ny, nz) of the full grid on the domain of phys
         when these arrays are a window of it (the spacing, the damping and
-        the Pt pseudo-step are the full grid's)."""
+        the Pt pseudo-step are the full grid's).  variant: V_* bits selecting
+        alternative readings of the iteration (0: the solver's)."""
         self.phys = phys
         self.nx, self.ny, self.nz = nx, ny, nz
         self.lib = _load()
         p = _Params()
         p.nx, p.ny, p.nz = nx, ny, nz
-        for name, _ in _Params._fields_[3:-10]:
+        for name, _ in _Params._fields_[3:-11]:
             setattr(p, name, float(getattr(phys, name)))
         if global_counts is not None:
             # a window of a (gx, gy, gz) grid on the full domain of phys
@@ -149,6 +161,7 @@ class Oracle:
         p.dpcap = int(bool(phys.dpcap))
         p.mech_off = int(bool(phys.mech_off))
         p.k0field = int(k0 is not None)
+        p.variant = int(variant)
         self._params = p
         self.ctx = self.lib.or_create(C.byref(p))
         if not self.ctx:
@@ -269,6 +282,7 @@ class Oracle:
                 self.refresh()
             nm = self.iteration(update_lp=True, norms=(it % nup == 0))
             if nm is not None:
+                _check_finite(nm, it)
                 nm["iter"] = it
                 self.history.append(nm)
                 last = nm
@@ -292,6 +306,7 @@ class Oracle:
             nm = self.iteration(update_lp=False, norms=want)
             if nm is None:
                 continue
+            _check_finite(nm, it)
             gv, gp = nm["f"], max(nm["rpt"], nm["rpf"])
             if self.ref is None:
                 self.ref = (gv, gp)
@@ -317,8 +332,18 @@ class Oracle:
         return 1.0 - np.exp(self.f["lp"])
 
 
+def _check_finite(nm, it):
+    bad = [k for k in NORM_NAMES if not np.isfinite(nm[k])]
+    if bad:
+        raise OracleDiverged(f"non-finite norms {bad} at iteration {it}")
+
+
 def rel_residual(gv, gp, g0):
-    """rho = max over groups with a nonzero initial norm of g/g0."""
+    """rho = max over groups with a nonzero initial norm of g/g0.  Raises
+    OracleDiverged if any norm is not finite (Python's max would drop a NaN
+    and report a diverged solve as converged)."""
+    if not all(np.isfinite(v) for v in (gv, gp, g0[0], g0[1])):
+        raise OracleDiverged(f"non-finite residual: g_V {gv}, g_P {gp}, reference {g0}")
     r = 0.0
     if g0[0] > 0:
         r = max(r, gv / g0[0])

@@ -48,7 +48,22 @@ typedef struct {
     int32_t ngx, ngy, ngz;
     /* Grid spacings of the full grid for such a window (0: l/n). */
     double hx, hy, hz;
+    /* Alternative readings of the iteration (OR_V_*), 0 for the readings
+     * the solver implements.  They change the pseudo-time path only, never
+     * the converged solution; tests use them to show why a reading was
+     * taken. */
+    int32_t variant;
 } or_params;
+
+/* beta_n r_Pt in the normal stresses evaluated at the updated Pt' instead of
+ * the iteration-k values the script uses. */
+#define OR_V_BETAN_UPDATED 1
+/* velocity pseudo-step as printed in the script, rho_i h^2 (1+beta_n)/(c_v mu_s),
+ * instead of dividing by (1+beta_n). */
+#define OR_V_DTV_PRINTED 2
+/* fluid-pressure pseudo-step from the cell's own k/mu_f, as printed, instead
+ * of the largest of the cell and its face neighbours. */
+#define OR_V_DTPF_CELL 4
 
 /* Solver state: every pointer is a dense FP64 array, x fastest.
  *   cells:    nx*ny*nz
@@ -448,6 +463,8 @@ static void porosity_update(or_ctx *c, const or_state *st, const double *ptn,
 static double dtau_v_cell(const or_ctx *c, double mus)
 {
     const or_params *p = &c->p;
+    if (p->variant & OR_V_DTV_PRINTED)
+        return p->rho_i * c->h * c->h * (1.0 + p->beta_n) / (p->c_v * mus);
     return p->rho_i * c->h * c->h / (p->c_v * mus * (1.0 + p->beta_n));
 }
 
@@ -455,6 +472,8 @@ static double dtau_pf_cell(const or_ctx *c, const or_state *st, int i, int j, in
 {
     const or_params *p = &c->p;
     double km = st->kc[IC(i, j, k)];
+    if (p->variant & OR_V_DTPF_CELL)
+        return c->h * c->h * (1.0 + p->beta_d * p->B / p->alpha) / (p->c_pf * km);
     if (i > 0)      km = dmax(km, st->kc[IC(i - 1, j, k)]);
     if (i < NX - 1) km = dmax(km, st->kc[IC(i + 1, j, k)]);
     if (j > 0)      km = dmax(km, st->kc[IC(i, j - 1, k)]);
@@ -471,17 +490,24 @@ static double dtau_pf_cell(const or_ctx *c, const or_state *st, int i, int j, in
  *   7: max |dV| over all three components                                   */
 #define OR_NNORMS 8
 
+/* Maxima that keep a NaN (a diverged iterate must not look converged). */
+static double nmax(double a, double b)
+{
+    if (a != a || b != b) return NAN;
+    return a > b ? a : b;
+}
+
 static double amax_diff(const double *a, const double *b, size_t n)
 {
     double m = 0.0;
-    for (size_t q = 0; q < n; ++q) m = dmax(m, fabs(a[q] - b[q]));
+    for (size_t q = 0; q < n; ++q) m = nmax(m, fabs(a[q] - b[q]));
     return m;
 }
 
 static double amax(const double *a, size_t n)
 {
     double m = 0.0;
-    for (size_t q = 0; q < n; ++q) m = dmax(m, fabs(a[q]));
+    for (size_t q = 0; q < n; ++q) m = nmax(m, fabs(a[q]));
     return m;
 }
 
@@ -515,7 +541,7 @@ void or_iteration(or_ctx *c, or_state *st, int update_lp, double *norms)
 
     if (norms) {
         or_residual(c, st, NULL, NULL, NULL, NULL, NULL);
-        norms[0] = dmax(amax(c->fx, c->nfx), dmax(amax(c->fy, c->nfy), amax(c->fz, c->nfz)));
+        norms[0] = nmax(amax(c->fx, c->nfx), nmax(amax(c->fy, c->nfy), amax(c->fz, c->nfz)));
         norms[1] = amax(c->rpt, c->nc);
         norms[2] = amax(c->rpf, c->nc);
     }
@@ -551,10 +577,11 @@ void or_iteration(or_ctx *c, or_state *st, int update_lp, double *norms)
                 c->pfn[q] = num / den;
             }
 
-    /* Stresses from V^k; their numerical-compressibility term takes r_Pt at
-     * the updated Pt' (the value the implicit pressure step drives to zero);
-     * momentum with the updated Pt'. */
-    total_pressure_residual(c, st, c->ptn);
+    /* Stresses from V^k with the numerical-compressibility term beta_n r_Pt
+     * of iteration k (r_Pt above, formed before the pressure update, as the
+     * script forms it); momentum with the updated Pt'. */
+    if (p->variant & OR_V_BETAN_UPDATED)
+        total_pressure_residual(c, st, c->ptn);
     stresses(c, st, 1);
     momentum(c, st, c->ptn);
 
@@ -611,7 +638,7 @@ void or_iteration(or_ctx *c, or_state *st, int update_lp, double *norms)
         norms[4] = amax_diff(c->ptn, st->pt, c->nc);
         norms[5] = amax_diff(c->pfn, st->pf, c->nc);
         norms[6] = amax_diff(c->vzn, st->vz, c->nfz);
-        norms[7] = dmax(norms[6], dmax(amax_diff(c->vxn, st->vx, c->nfx), amax_diff(c->vyn, st->vy, c->nfy)));
+        norms[7] = nmax(norms[6], nmax(amax_diff(c->vxn, st->vx, c->nfx), amax_diff(c->vyn, st->vy, c->nfy)));
     }
 
     memcpy(st->pt, c->ptn, c->nc * sizeof(double));
@@ -664,8 +691,11 @@ void or_begin_step(or_ctx *c, or_state *st, int update_history)
  *   tau_II   from the deviatoric stress of the current state without the
  *            numerical-compressibility term (edges averaged to centres)
  *   Mn_visc  = mu0 / (1 + (tau_II/tau0)^(n-1))  (power law, eq (24)) or mu0
- *   cap      : tau_y = max(C cos(f) + (Pt-Pf) sin(f), tau_y_min); if
- *              tau_II > tau_y then Mn_new = min(Mn_visc, Mn tau_y/tau_II)
+ *   cap      : tau_y = max(C cos(f) + (Pt-Pf) sin(f), tau_y_min);
+ *              Mn_new = min(Mn_visc, Mn tau_y/tau_II) where tau_II > 0, i.e.
+ *              the viscosity that would put the present strain rate on the
+ *              yield surface, where that is below the viscous one (a cell
+ *              at the yield surface keeps its Mn: yielded fixed points)
  *   Mn       = exp(r_mu ln Mn_new + (1-r_mu) ln Mn);  mu_s = Mn phi0 cmu
  * first = 1 takes the new values without relaxation.  The stress invariant
  * uses the coefficients in force before this refresh.                       */
@@ -712,7 +742,7 @@ void or_refresh(or_ctx *c, or_state *st, int first, double r_eta, double r_mu)
                     }
                     if (p->dpcap) {
                         double ty = dmax(p->coh * cosf + (st->pt[q] - st->pf[q]) * sinf, p->tau_y_min);
-                        if (tii > ty) mn_new = dmin(mn_new, st->mn[q] * ty / tii);
+                        if (tii > 0.0) mn_new = dmin(mn_new, st->mn[q] * ty / tii);
                     }
                 }
                 double mn = first ? mn_new : exp(r_mu * log(mn_new) + (1.0 - r_mu) * log(st->mn[q]));

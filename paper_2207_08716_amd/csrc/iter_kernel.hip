@@ -239,15 +239,15 @@ __global__ __launch_bounds__((sweep_bx<T, MODE, NORMS>() * (HV ? HV : sweep_by<T
             const T dzv = (vz_n - vz_c) * c.dzi;
             const T divv = dxv + dyv + dzv;
             const T dtp = c.dtaupt_c * mu_c;
-            T rimp;
+            // r_Pt of iteration k: the numerical-compressibility term of the
+            // stresses takes it before the pressure update
             if constexpr (CORR) {
                 // d Pt' = [d Pt - dtau (div dV + r_Pt(x) - beta_d alpha dPf/dt - dPf chi)]
                 //         / (1 + dtau (beta_d/dt + chi)); chi is a stored field here
                 chi = eta;
                 ptn = (pt - dtp * (divv + pto - c.beta_d * c.alpha * pf_c * c.dti - pf_c * chi)) /
                       (one + dtp * (c.beta_d * c.dti + chi));
-                rimp = pto + divv + c.beta_d * (ptn - c.alpha * pf_c) * c.dti + (ptn - pf_c) * chi;
-                if (WNORM) rpt_k = pto + divv + c.beta_d * (pt - c.alpha * pf_c) * c.dti + (pt - pf_c) * chi;
+                rpt_k = pto + divv + c.beta_d * (pt - c.alpha * pf_c) * c.dti + (pt - pf_c) * chi;
             } else {
                 chi = one / (eta * s_c);
                 if (RESID || c.mech_off) {
@@ -256,14 +256,13 @@ __global__ __launch_bounds__((sweep_bx<T, MODE, NORMS>() * (HV ? HV : sweep_by<T
                     ptn = (pt - dtp * (divv + c.beta_d * (-pto - c.alpha * (pf_c - pfo)) * c.dti - pf_c * chi)) /
                           (one + dtp * (c.beta_d * c.dti + chi));
                 }
-                rimp = divv + c.beta_d * ((ptn - pto) - c.alpha * (pf_c - pfo)) * c.dti + (ptn - pf_c) * chi;
-                if (WNORM) rpt_k = divv + c.beta_d * ((pt - pto) - c.alpha * (pf_c - pfo)) * c.dti + (pt - pf_c) * chi;
+                rpt_k = divv + c.beta_d * ((pt - pto) - c.alpha * (pf_c - pfo)) * c.dti + (pt - pf_c) * chi;
                 rg = c.rhofg * (one - s_c) + c.rhosg * s_c;
             }
             const T xi = mu_c * c.gdts_inv;
             const T b = two * mu_c / (one + xi);
             const T d3 = divv * c.third;
-            const T comp = RESID ? zero : c.beta_n * rimp;
+            const T comp = RESID ? zero : c.beta_n * rpt_k;
             txx = b * ((dxv - d3) + comp);
             tyy = b * ((dyv - d3) + comp);
             tzz = b * ((dzv - d3) + comp);

@@ -172,7 +172,9 @@ __global__ __launch_bounds__(RW * RH) void k_refresh_tiled(Geom g, Coef c, Refre
             }
             if (r.dpcap) {
                 const double tyl = fmax(r.coh_cos + (cc.pt - cc.pf) * r.sin_f, r.tau_y_min);
-                if (tii > tyl) mn_new = fmin(mn_new, cc.mn * tyl / tii);
+                // the viscosity that puts the present strain rate on the
+                // yield surface, where it is below the viscous one
+                if (tii > 0.0) mn_new = fmin(mn_new, cc.mn * tyl / tii);
             }
             const double mnr = r.first ? mn_new : exp(r.r_mu * log(mn_new) + (1.0 - r.r_mu) * log(cc.mn));
             a.kc[o] = kc;
