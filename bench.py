@@ -1,19 +1,21 @@
 """Benchmark: effective memory throughput of the PT iteration at 511^3.
 
-One "step" is one PT iteration of the thesis schedule (article 1, section 2.2;
-appendix two-phase script) on the 511^3 porosity-anomaly workload (two
-Gaussian anomalies, lognormal k0, Drucker-Prager cap), FP64: the fused sweep
-updates all velocities, both pressures and the porosity every iteration, the
-lagged coefficients are refreshed every nup = 15 iterations and the residual
-norms taken every nup iterations (both amortised in the timing, as the thesis's
-t_it = time/niter does).
+One "step" is one refresh cycle of the thesis schedule (article 1, section
+2.2; appendix two-phase script) on the 511^3 porosity-anomaly workload (two
+Gaussian anomalies, lognormal k0, Drucker-Prager cap), FP64: a Picard refresh
+of the lagged coefficients followed by nup = 15 fused PT iterations, each
+updating all velocities, both pressures and the porosity, the last one also
+reducing the residual norms.  Warm-up and timed region are whole cycles, so
+the refresh and the norms are amortised exactly as in the thesis's
+t_it = time/niter.
 
 value = T_eff = A_eff / t_it with A_eff = (2*12 + 1) N p (eqs (37)-(38)),
-N = 511^3 cells, p = 8 bytes.
+N = 511^3 cells, p = 8 bytes, t_it = time of the timed cycles / (15 K).
 
 Prints one JSON line.  Options: --gpus N (only 1: the build runs on one GPU),
---steps K, --warmup W, --n (grid size), --no-cpu (skip the CPU baseline),
---ttt-n (size of the mixed-vs-FP64 time-to-tolerance comparison; 0 skips it).
+--steps K and --warmup W (refresh cycles of 15 iterations), --n (grid size),
+--no-cpu (skip the CPU baseline), --ttt-n (size of the mixed-vs-FP64
+time-to-tolerance comparison; 0 skips it).
 """
 from __future__ import annotations
 
@@ -50,21 +52,48 @@ def measured_traffic(n: int):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(cfg, fields, n_iter: int = 2):
-    """The FP64 CPU reference timed on this host: thesis schedule on the same
-    511^3 workload, a bounded sample of n_iter iterations after the first
-    (refreshing) one."""
+def _oracle_t_it(cfg, fields, warm=2, timed=15):
+    """Per-iteration times of the FP64 CPU reference on a workload: thesis
+    schedule from the initial state, `warm` untimed iterations, then `timed`
+    iterations timed one by one (15 = one refresh cycle: the refresh before
+    iteration 16 falls inside).  Returns (setup s, list of iteration s)."""
     import oracle
-    from paper_2207_08716_amd import teff
     t0 = time.perf_counter()
     o = oracle.Oracle(cfg.phys, cfg.nx, cfg.ny, cfg.nz, fields["phi"], fields["k0"])
     o.begin_step()
-    o.iterate(1)
+    o.iterate(warm)
     t1 = time.perf_counter()
-    o.iterate(n_iter)
-    t2 = time.perf_counter()
-    t_it = (t2 - t1) / n_iter
+    ts = []
+    for _ in range(timed):
+        a = time.perf_counter()
+        o.iterate(1)
+        ts.append(time.perf_counter() - a)
     del o
+    return t1 - t0, ts
+
+
+def cpu_baseline(cfg, fields, ctx_n=255, single_n=64):
+    """The FP64 CPU reference timed on this host's cores: on the same workload
+    (2 warm-up + 15 timed thesis-schedule iterations, one whole refresh cycle),
+    on the same recipe at ctx_n^3, and single-threaded at single_n^3 for
+    context.  value: T_eff of the mean t_it on the workload."""
+    import statistics
+    import oracle
+    from paper_2207_08716_amd import inputs, teff
+    threads = oracle.num_threads()
+    setup, ts = _oracle_t_it(cfg, fields)
+    t_it = sum(ts) / len(ts)
+    out_ctx = {}
+    for label, n, nthreads in (("all_threads", ctx_n, threads), ("single_thread", single_n, 1)):
+        c = inputs.config_mixed(n)
+        oracle.set_num_threads(nthreads)
+        try:
+            _s, tc = _oracle_t_it(c, inputs.initial_fields(c))
+        finally:
+            oracle.set_num_threads(threads)
+        m = sum(tc) / len(tc)
+        out_ctx[f"{label}_{n}"] = {"n": n, "threads": nthreads, "t_it_s": round(m, 5),
+                                    "t_eff_gbs": round(teff.t_eff_gbs(c.ncell, 8, m), 3)}
     model = ""
     try:
         for line in open("/proc/cpuinfo"):
@@ -76,12 +105,14 @@ def cpu_baseline(cfg, fields, n_iter: int = 2):
     return {
         "value": round(teff.t_eff_gbs(cfg.ncell, 8, t_it), 3),
         "unit": "GB/s",
-        "cores": oracle.num_threads(),
+        "cores": threads,
         "cpu_model": model,
         "kind": "oracle",
-        "sample": f"{n_iter} thesis-schedule PT iterations of the same {cfg.nx}^3 FP64 workload "
-                  f"after one warm-up iteration (setup {t1 - t0:.1f} s); t_it = {t_it:.3f} s",
-        "t_it_s": t_it,
+        "sample": f"15 thesis-schedule PT iterations (one refresh cycle) of the same {cfg.nx}^3 FP64 workload "
+                  f"after 2 warm-up iterations (set-up {setup:.1f} s); t_it = mean of the 15",
+        "t_it_s": round(t_it, 4),
+        "t_it_median_s": round(statistics.median(ts), 4),
+        "context": out_ctx,
     }
 
 
@@ -228,14 +259,13 @@ def adjoint_measure(n, n_steps=10, n_picard=5, rtol=1e-10, ns=64, checkpoint=Fal
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=150)
-    ap.add_argument("--warmup", type=int, default=30)
+    ap.add_argument("--steps", type=int, default=10, help="timed refresh cycles (15 PT iterations each)")
+    ap.add_argument("--warmup", type=int, default=2, help="untimed refresh cycles before timing")
     ap.add_argument("--n", type=int, default=511)
     ap.add_argument("--workload", choices=("anomaly", "waves"), default="anomaly",
                     help="anomaly: two Gaussian anomalies on the unit cube (default); waves: the "
                          "porosity-wave domain (30^3, three sources, dt 5e-4)")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=2)
     ap.add_argument("--ttt-n", type=int, default=127,
                     help="grid size of the mixed-vs-FP64 time-to-tolerance comparison (0: skip)")
     ap.add_argument("--adjoint-n", type=int, default=0,
@@ -276,19 +306,20 @@ def main(argv=None):
         e1.synchronize()
         return e0.elapsed_time(e1) / 1e3
 
-    # ---- warm-up: first refresh, then W thesis iterations ------------------
+    nup = cfg.phys.nup
+    # ---- warm-up: W whole refresh cycles (W nup thesis iterations) ---------
     g.begin_step(update_history=False)
-    g.iterate(args.warmup)
+    g.iterate(args.warmup * nup)
     torch.cuda.synchronize()
 
-    # ---- timed region: exactly K thesis-schedule iterations ----------------
+    # ---- timed region: exactly K refresh cycles (K nup iterations) ---------
     torch.cuda.synchronize()
     t_wall0 = time.perf_counter()
-    t_steps = timed(lambda k: g.iterate(k), args.steps)
+    t_steps = timed(lambda k: g.iterate(k * nup), args.steps)
     torch.cuda.synchronize()
     t_wall = time.perf_counter() - t_wall0
-    norms = g.last_norms() if args.steps + args.warmup >= cfg.phys.nup else None
-    t_it = t_steps / args.steps
+    norms = g.last_norms() if args.steps >= 1 else None
+    t_it = t_steps / (args.steps * nup)
     value = teff.t_eff_gbs(cfg.ncell, 8, t_it)
 
     # ---- dominant kernel alone: the fused sweep (thesis variant), measured
@@ -320,7 +351,9 @@ def main(argv=None):
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(t_it * 1e3, 4),
+        "ms_per_step": round(t_steps / args.steps * 1e3, 4),
+        "iterations_per_step": nup,
+        "t_it_ms": round(t_it * 1e3, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -333,6 +366,7 @@ def main(argv=None):
             (f"{n}^3 porosity-wave domain (L=30, three sources of width 1), scalar k0, "
              "Drucker-Prager cap, dt 5e-4, thesis PT schedule (refresh/norms every 15)"),
             "n": n, "cells": cfg.ncell, "precision": "fp64", "schedule": "thesis",
+            "step": f"one refresh cycle: refresh + {nup} PT iterations (norms on the last)",
             "parallelism": "single GPU",
         },
         "pct_hbm_peak": round(100 * value / HBM_PEAK_GBS, 2),
@@ -368,7 +402,7 @@ def main(argv=None):
                                              checkpoint=args.adjoint_checkpoint, mixed=args.adjoint_mixed)
 
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(cfg, fields, args.cpu_iters)
+        out["cpu_baseline"] = cpu_baseline(cfg, fields)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)

@@ -26,9 +26,10 @@
  *   pt_field_elems() doubles.  Cells use i < nx, j < ny, k < nz; x-faces
  *   i <= nx; y-faces j <= ny; z-faces k <= nz; xy-edges i <= nx, j <= ny;
  *   xz-edges i <= nx, k <= nz; yz-edges j <= ny, k <= nz.  Entries outside a
- *   field's extent are never written; the kernels may read them (every load
- *   stays inside the buffer) and ignore their values.  Base pointers must be
- *   256-byte aligned; row_pitch >= nx + 1.
+ *   field's extent are never written, except by pt_reset_state, which fills
+ *   whole buffers; the kernels may read them (every load stays inside the
+ *   buffer) and ignore their values.  Base pointers must be 256-byte aligned;
+ *   row_pitch >= nx + 1.
  * State.  The nine iterated fields (PT_VX .. PT_RZ) are double-buffered
  *   (Jacobi iteration: no point reads a value written in the same sweep).
  *   Bind both copies (copy 0 and 1); pt_current() tells which copy holds the
@@ -38,9 +39,15 @@
  *   (default: the null stream), except where marked "synchronises".
  * Errors.  Every call returns a pt_status and never throws.  PT_EINVAL: a
  *   bad argument (nothing was launched).  PT_EDEVICE: a HIP error.
- *   PT_EDIVERGED: a non-finite norm.  PT_ENOTCONV: an iteration limit was
- *   hit (the state is valid).  pt_last_error() holds a message for the last
- *   failure on the handle.
+ *   PT_EDIVERGED: a non-finite norm.  PT_EDOMAIN: the porosity left (0, 1)
+ *   (ln(1-phi) not in (-inf, 0)); the porosity step and the iterations that
+ *   compute norms flag it, and the next call that reads norms,
+ *   pt_picard_step or pt_set_porosity reports it.  PT_EDIVERGED, PT_EDOMAIN and PT_EDEVICE put the handle in
+ *   its error state: every call that launches work returns PT_ESTATE until
+ *   pt_begin_step, pt_set_params, pt_reset_state or pt_set_porosity (the
+ *   caller repairs or reloads the fields first).  PT_ENOTCONV: an iteration
+ *   limit was hit (the state is valid).  pt_last_error() holds a message for
+ *   the last failure on the handle.
  * Threads.  One handle must not be used by two threads at once; distinct
  *   handles are independent.
  */
@@ -90,7 +97,12 @@ typedef enum {
 
 /* Flags of pt_params.flags */
 #define PT_F_POWERLAW 1u   /* eq (24): mu_s = mu0 / (1 + (tau_II/tau0)^(n-1))        */
-#define PT_F_DPCAP    2u   /* Drucker-Prager cap of the lagged viscosity             */
+#define PT_F_DPCAP    2u   /* Drucker-Prager cap of the lagged viscosity: at a refresh,
+                               Mn_new = min(Mn_visc, Mn tau_y / tau_II) with
+                               tau_y = max(C cos f + (Pt - Pf) sin f, tau_y_min), the
+                               viscosity that puts the present strain rate on the yield
+                               surface where it is below the viscous one (the paper has
+                               no cap; its plasticity is the power law of eq (24))  */
 #define PT_F_K0FIELD  4u   /* k0 is the per-cell field PT_K0, else the scalar kmuf0   */
 #define PT_F_MECHOFF  8u   /* freeze V and Pt (linear fluid-pressure diffusion limit) */
 
@@ -131,7 +143,9 @@ typedef struct {
 } pt_norms;
 
 /* Create a handle for an nx x ny x nz cell grid (each >= 2) with the given
- * row pitch (>= nx + 1, in elements) and parameters (copied). */
+ * row pitch (>= nx + 1, in elements) and parameters (copied).  The launch
+ * shapes use the compute-unit count of the current device (256 if none can
+ * be queried). */
 pt_status pt_create(int32_t nx, int32_t ny, int32_t nz, int64_t row_pitch,
                     const pt_params* params, pt_grid** out);
 pt_status pt_destroy(pt_grid* g);
@@ -216,8 +230,49 @@ pt_status pt_set_residual_reference(pt_grid* g, double gv, double gp);
 
 /* Porosity time step after a converged Picard stage: ln(1-phi) =
  * ln(1-phi)o - dt dphi/dt(V, Pt, Pf) (eq (22)) with the present solid
- * fraction. */
+ * fraction.  A cell leaving (0, 1) is flagged (PT_EDOMAIN at the next norm
+ * read or at the end of pt_picard_step). */
 pt_status pt_porosity_step(pt_grid* g);
+
+/* Initial state of a run (the zero state of article 1's set-ups): V, R, Pt,
+ * Pf (both copies), old pressures, stress history and its divergence Fo
+ * <- 0; Mn <- mu0; the lagged coefficients take their values before the
+ * first refresh (k/mu_f <- kmuf0, eta_phi <- 1, mu_s <- mu0 phi0 cmu).
+ * ln(1-phi), its old value and k0 keep their contents (the present copy of
+ * ln(1-phi) becomes copy 0); set the porosity with pt_set_porosity.
+ * Clears the counters (pt_counters), the error state and the domain flag;
+ * the next refresh is a run's first (no relaxation), the mixed solve's FP32
+ * damped residual restarts at zero.  Writes whole field buffers. */
+pt_status pt_reset_state(pt_grid* g);
+
+/* ln(1-phi) and its old value <- ln(1 - phi) on the cells (the log-space
+ * porosity of eq (22)), from phi_dev: an FP64 device buffer in the field
+ * layout (cells), 256-byte aligned, owned by the caller.  Synchronises.
+ * PT_EDOMAIN if some phi is not in (0, 1) (the values are written anyway).
+ * Clears the error state first. */
+pt_status pt_set_porosity(pt_grid* g, const void* phi_dev);
+
+/* Host-side counters of a handle, for resuming a run on a new handle that
+ * binds the same buffers: get them, destroy the handle, create a new one,
+ * bind the same field and workspace buffers, set them; the run then
+ * continues bit for bit.  iter: iterations of the present step (decides the
+ * thesis schedule's refreshes and checks); refreshed: a refresh has run
+ * (later ones relax); ref_set, ref_v, ref_p: the step's residual reference
+ * (pt_solve_linear); cur: the copy holding the present value of each
+ * double-buffered field; mixed_copy, mixed_clean: the mixed workspace copy
+ * that holds the FP32 damped residual and whether the workspace is
+ * initialised (kept only if the mixed workspace is bound when set). */
+typedef struct {
+    int32_t version;                /* PT_ABI_VERSION                                  */
+    int32_t refreshed;
+    int64_t iter;
+    int32_t ref_set, mixed_copy;
+    double ref_v, ref_p;
+    int32_t cur[PT_NPING];
+    int32_t mixed_clean;
+} pt_counters;
+pt_status pt_get_counters(const pt_grid* g, pt_counters* out);
+pt_status pt_set_counters(pt_grid* g, const pt_counters* in);
 
 /* One physical step of the Picard schedule (the thesis's M-P driver): the
  * step set-up of pt_begin_step(update_history), then n_picard stages of

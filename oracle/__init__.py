@@ -106,6 +106,7 @@ def _load():
         lib.or_last_stresses.argtypes = [C.c_void_p] + [P(C.c_double)] * 6
         lib.or_last_fluxes.argtypes = [C.c_void_p] + [P(C.c_double)] * 3
         lib.or_num_threads.restype = C.c_int
+        lib.or_set_num_threads.argtypes = [C.c_int]
         lib.or_heat1d_step.restype = C.c_int
         lib.or_heat1d_step.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double,
                                        C.c_double, P(C.c_double), P(C.c_double), C.c_int]
@@ -355,6 +356,11 @@ def rel_residual(gv, gp, g0):
 def num_threads() -> int:
     """Threads the oracle's OpenMP loops use."""
     return int(_load().or_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's following OpenMP loops (timing only)."""
+    _load().or_set_num_threads(int(n))
 
 
 def heat1d_step(Ut, U0, dx, dt, lam_rho_cp, eps, max_iter=10_000_000):

@@ -176,6 +176,16 @@ int or_num_threads(void)
 #endif
 }
 
+/* Set the number of threads of the following OpenMP loops (timing only). */
+void or_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* Background density x gravity: rho_bg g = phi0 rho_f g + (1-phi0) rho_s g
  * (the script's rogBG).  Pressures are perturbations from the lithostatic
  * state of this density. */

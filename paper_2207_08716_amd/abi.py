@@ -42,11 +42,19 @@ class Norms(C.Structure):
     _fields_ = [(n, C.c_double) for n in ("f", "rpt", "rpf", "dl", "dpt", "dpf", "dvz", "dv")]
 
 
+class Counters(C.Structure):
+    _fields_ = [("version", C.c_int32), ("refreshed", C.c_int32), ("iter", C.c_int64),
+                ("ref_set", C.c_int32), ("mixed_copy", C.c_int32),
+                ("ref_v", C.c_double), ("ref_p", C.c_double),
+                ("cur", C.c_int32 * NPING), ("mixed_clean", C.c_int32)]
+
+
 EXPORTS = ["pt_create", "pt_destroy", "pt_field_elems", "pt_bind_field", "pt_workspace_size",
            "pt_bind_workspace", "pt_set_stream", "pt_set_progress", "pt_set_params", "pt_current", "pt_begin_step",
            "pt_refresh", "pt_iteration", "pt_iterate", "pt_last_norms", "pt_solve_linear",
            "pt_residual_reference", "pt_set_residual_reference",
-           "pt_porosity_step", "pt_picard_step", "pt_mixed_workspace_size", "pt_bind_mixed_workspace", "pt_residual",
+           "pt_porosity_step", "pt_reset_state", "pt_set_porosity", "pt_get_counters", "pt_set_counters",
+           "pt_picard_step", "pt_mixed_workspace_size", "pt_bind_mixed_workspace", "pt_residual",
            "pt_solve_mixed", "pt_adjoint_workspace_size", "pt_bind_adjoint_workspace", "pt_set_log_k0",
            "pt_misfit", "pt_adjoint_stage", "pt_adjoint_tape_size", "pt_adjoint_run", "pt_copy", "pt_status_str", "pt_last_error", "pt_abi_version"]
 
@@ -90,6 +98,10 @@ def load(path: str = LIB_PATH):
     lib.pt_last_norms.argtypes = [vp, P(Norms)]
     lib.pt_solve_linear.argtypes = [vp, C.c_double, C.c_int64, P(C.c_int64), P(C.c_double)]
     lib.pt_porosity_step.argtypes = [vp]
+    lib.pt_reset_state.argtypes = [vp]
+    lib.pt_set_porosity.argtypes = [vp, vp]
+    lib.pt_get_counters.argtypes = [vp, P(Counters)]
+    lib.pt_set_counters.argtypes = [vp, P(Counters)]
     lib.pt_picard_step.argtypes = [vp, C.c_int32, C.c_int32, C.c_double, C.c_int64, C.c_int32, C.c_double,
                                    P(C.c_int64), P(C.c_double)]
     lib.pt_residual_reference.argtypes = [vp, P(C.c_double), P(C.c_double)]

@@ -2,8 +2,8 @@
 
 LogKMisfit.apply(logk0, problem) runs one linear Picard stage from the
 problem's initial state with k0 = exp(logk0) and returns the sensor misfit
-J = 1/2 sum_s (Pf_s - d_s)^2; backward returns dJ/d(logk0) from the stage
-adjoint (pt_adjoint_stage).
+J = 1/2 sum_s (Pf_s - d_s)^2; the stage adjoint (pt_adjoint_stage) runs with
+the forward and backward returns its dJ/d(logk0).
 
 LogKMisfitRun.apply(logk0, run_problem) does the same for a run of Picard
 steps x stages (pt_adjoint_run: recorded forward, then the reverse sweep; the
@@ -40,19 +40,24 @@ class StageProblem:
 
 
 class LogKMisfit(torch.autograd.Function):
+    """The gradient is computed with the forward (the stage adjoint needs the
+    grid in the state the forward left, which a later forward on the same
+    problem would overwrite) and kept for backward."""
+
     @staticmethod
     def forward(ctx, logk0: torch.Tensor, problem: StageProblem):
         J = problem.forward(logk0.detach())
-        ctx.problem = problem
+        p = problem
+        _J, grad, _it, _rho, ok = p.grid.adjoint_stage(p.sensors, p.d_obs, p.rtol, p.max_iter)
+        if not ok:
+            raise RuntimeError("adjoint solve did not converge")
+        ctx.save_for_backward(grad.clone())
         return logk0.new_tensor(J)
 
     @staticmethod
     def backward(ctx, grad_out):
-        p = ctx.problem
-        _J, grad, _it, _rho, ok = p.grid.adjoint_stage(p.sensors, p.d_obs, p.rtol, p.max_iter)
-        if not ok:
-            raise RuntimeError("adjoint solve did not converge")
-        return grad_out * grad.clone(), None
+        (grad,) = ctx.saved_tensors
+        return grad_out * grad, None
 
 
 class RunProblem:

@@ -32,6 +32,7 @@ struct pt_grid {
     bool ref_set = false;
     bool refreshed = false;    // any refresh done on this handle
     bool norms_pending = false;
+    bool broken = false;       // PT_ESTATE: a divergence, domain or device error occurred
     pt_progress_fn progress = nullptr;   // per-stage report of long calls
     void* progress_user = nullptr;
     std::string err;
@@ -39,14 +40,21 @@ struct pt_grid {
 
 namespace {
 
+// Failures that leave the state unusable put the handle in its error state
+// (PT_ESTATE) until pt_set_params, pt_begin_step, pt_reset_state or
+// pt_set_porosity.
 pt_status fail(pt_grid* g, pt_status s, const char* msg) {
-    if (g) g->err = msg;
+    if (g) {
+        g->err = msg;
+        if (s == PT_EDIVERGED || s == PT_EDOMAIN || s == PT_EDEVICE) g->broken = true;
+    }
     return s;
 }
 
 pt_status hip_fail(pt_grid* g, hipError_t e, const char* where) {
     if (g) {
         g->err = std::string(where) + ": " + hipGetErrorString(e);
+        g->broken = true;
     }
     return PT_EDEVICE;
 }
@@ -119,6 +127,7 @@ RefreshCoef make_refresh(const pt_grid* g, double r_eta, double r_mu) {
 }
 
 size_t ws_needed(const pt_grid* g);
+double* domain_flag(pt_grid* g);
 
 double* cur(pt_grid* g, int f) { return f < PT_NPING ? g->f[f][g->cur[f]] : g->f[f][0]; }
 double* alt(pt_grid* g, int f) { return g->f[f][1 - g->cur[f]]; }
@@ -157,6 +166,7 @@ AuxPtrs aux(pt_grid* g) {
     a.mus = cur(g, PT_MUS);
     a.k0 = g->f[PT_K0][0];
     a.lp_o = alt(g, PT_LP);
+    a.domain = domain_flag(g);
     return a;
 }
 
@@ -166,17 +176,34 @@ const std::initializer_list<int> kAllCore = {PT_VX, PT_VY, PT_VZ, PT_PT, PT_PF, 
                                             PT_KC, PT_ETA, PT_MUS};
 
 pt_status check_ready(pt_grid* g) {
+    if (g->broken) {
+        const std::string why = g->err;
+        g->err = "handle in error state (" + why + "); call pt_begin_step, pt_set_params, pt_reset_state or pt_set_porosity";
+        g->err.resize(std::min<size_t>(g->err.size(), 400));
+        return PT_ESTATE;
+    }
     if (!bound(g, kAllCore, true)) return fail(g, PT_EINVAL, "not every field (both copies of the iterated ones) is bound");
     if ((g->prm.flags & PT_F_K0FIELD) && !g->f[PT_K0][0]) return fail(g, PT_EINVAL, "PT_F_K0FIELD set but PT_K0 not bound");
     if (!g->ws || g->ws_bytes < ws_needed(g)) return fail(g, PT_EINVAL, "workspace not bound or too small");
     return PT_OK;
 }
 
-// Workspace layout (doubles): [partials: n_blocks * 8][norms: 8], padded to
-// a multiple of 256 bytes.
+// Workspace layout (doubles): [partials: n_blocks * 8][norms: 8][domain
+// flag: 1], padded to a multiple of 256 bytes.  The flag is set (to 1) by the
+// kernels that write ln(1-phi) where phi leaves (0, 1).
 size_t ws_needed(const pt_grid* g) {
-    const int64_t head = norm_blocks(g->geom) * NNORM + NNORM;
+    const int64_t head = norm_blocks(g->geom) * NNORM + NNORM + 1;
     return (size_t)((head + 31) / 32 * 32) * sizeof(double);
+}
+
+double* domain_flag(pt_grid* g) {
+    return g->ws ? static_cast<double*>(g->ws) + norm_blocks(g->geom) * NNORM + NNORM : nullptr;
+}
+
+pt_status clear_domain(pt_grid* g) {
+    hipError_t e = launch_fill(domain_flag(g), 0.0, 1, g->stream);
+    if (e != hipSuccess) return hip_fail(g, e, "domain flag clear");
+    return PT_OK;
 }
 
 pt_status refresh_impl(pt_grid* g, double r_eta, double r_mu) {
@@ -202,6 +229,7 @@ SweepPtrs<double> sweep_ptrs(pt_grid* g) {
     p.pt_o = alt(g, PT_PT); p.pf_o = alt(g, PT_PF); p.lp_o = alt(g, PT_LP);
     p.rx_o = alt(g, PT_RX); p.ry_o = alt(g, PT_RY); p.rz_o = alt(g, PT_RZ);
     p.partials = static_cast<double*>(g->ws);
+    p.domain = domain_flag(g);
     return p;
 }
 
@@ -241,17 +269,30 @@ int64_t mx_box(const pt_grid* g) { return g->geom.S * (int64_t)(g->geom.nz + 1);
 size_t mx_needed(const pt_grid* g) { return (size_t)(MX_NBOX * mx_box(g)) * sizeof(float); }
 float* mx(pt_grid* g, int b) { return g->mws + (int64_t)b * mx_box(g); }
 
+// The eight reduced norms and the domain flag (copied together).
 pt_status read_norms(pt_grid* g, pt_norms* out) {
-    double host[NNORM];
+    double host[NNORM + 1];
     hipError_t e = hipMemcpyAsync(host, static_cast<double*>(g->ws) + norm_blocks(g->geom) * NNORM, sizeof(host),
                                   hipMemcpyDeviceToHost, g->stream);
+    const hipError_t es = hipStreamSynchronize(g->stream);   // also on a failed copy: host is local
+    if (e == hipSuccess) e = es;
     if (e != hipSuccess) return hip_fail(g, e, "norms copy");
-    e = hipStreamSynchronize(g->stream);
-    if (e != hipSuccess) return hip_fail(g, e, "norms sync");
     out->f = host[0]; out->rpt = host[1]; out->rpf = host[2]; out->dl = host[3];
     out->dpt = host[4]; out->dpf = host[5]; out->dvz = host[6]; out->dv = host[7];
-    for (double v : host)
-        if (!std::isfinite(v)) return fail(g, PT_EDIVERGED, "non-finite residual norm");
+    for (int q = 0; q < NNORM; ++q)
+        if (!std::isfinite(host[q])) return fail(g, PT_EDIVERGED, "non-finite residual norm");
+    if (host[NNORM] != 0.0) return fail(g, PT_EDOMAIN, "porosity left (0, 1): ln(1-phi) not in (-inf, 0)");
+    return PT_OK;
+}
+
+// The domain flag alone (synchronises).
+pt_status read_domain(pt_grid* g) {
+    double flag = 0.0;
+    hipError_t e = hipMemcpyAsync(&flag, domain_flag(g), sizeof(double), hipMemcpyDeviceToHost, g->stream);
+    const hipError_t es = hipStreamSynchronize(g->stream);
+    if (e == hipSuccess) e = es;
+    if (e != hipSuccess) return hip_fail(g, e, "domain flag copy");
+    if (flag != 0.0) return fail(g, PT_EDOMAIN, "porosity left (0, 1): ln(1-phi) not in (-inf, 0)");
     return PT_OK;
 }
 
@@ -293,6 +334,13 @@ pt_status pt_create(int32_t nx, int32_t ny, int32_t nz, int64_t row_pitch, const
     g->prm = *params;
     std::memset(g->f, 0, sizeof(g->f));
     std::memset(g->cur, 0, sizeof(g->cur));
+    // compute units of the current device for the launch cost model (the
+    // default where no device can be queried; no error is left behind)
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+        g->geom.cus = cus;
+    (void)hipGetLastError();
     make_coef(g);
     *out = g;
     return PT_OK;
@@ -347,6 +395,7 @@ pt_status pt_set_params(pt_grid* g, const pt_params* params) {
     if (!valid_params(params)) return fail(g, PT_EINVAL, "invalid parameters");
     g->prm = *params;
     make_coef(g);
+    g->broken = false;
     return PT_OK;
 }
 
@@ -358,8 +407,15 @@ pt_status pt_current(const pt_grid* g, int32_t field, int32_t* copy) {
 
 pt_status pt_begin_step(pt_grid* g, int32_t update_history) {
     if (!g) return PT_EINVAL;
+    g->broken = false;
     pt_status st = check_ready(g);
     if (st != PT_OK) return st;
+    st = clear_domain(g);
+    if (st != PT_OK) return st;
+    // the FP32 damped residual of the mixed solves restarts with the step, so
+    // that a mixed step depends only on the state it starts from
+    g->mws_clean = false;
+    g->mx_copy = 0;
     const AuxPtrs a = aux(g);
     hipError_t e = launch_begin_step(g->geom, g->coef, a, update_history, g->stream);
     if (e != hipSuccess) return hip_fail(g, e, "begin_step");
@@ -476,6 +532,87 @@ pt_status pt_porosity_step(pt_grid* g) {
     hipError_t e = launch_porosity_step(g->geom, g->coef, a, g->stream);
     if (e != hipSuccess) return hip_fail(g, e, "porosity_step");
     g->cur[PT_LP] ^= 1;
+    return PT_OK;
+}
+
+pt_status pt_set_porosity(pt_grid* g, const void* phi_dev) {
+    if (!g || !phi_dev) return PT_EINVAL;
+    if (reinterpret_cast<uintptr_t>(phi_dev) & 255u) return fail(g, PT_EINVAL, "porosity buffer unaligned");
+    g->broken = false;
+    pt_status st = check_ready(g);
+    if (st != PT_OK) return st;
+    st = clear_domain(g);
+    if (st != PT_OK) return st;
+    hipError_t e = launch_set_porosity(g->geom, static_cast<const double*>(phi_dev), cur(g, PT_LP), cur(g, PT_LPO),
+                                       domain_flag(g), g->stream);
+    if (e != hipSuccess) return hip_fail(g, e, "set porosity");
+    return read_domain(g);
+}
+
+pt_status pt_reset_state(pt_grid* g) {
+    if (!g) return PT_EINVAL;
+    g->broken = false;
+    pt_status st = check_ready(g);
+    if (st != PT_OK) return st;
+    const int64_t n = g->geom.S * (int64_t)(g->geom.nz + 1);
+    const pt_params& p = g->prm;
+    const int zero_fields[] = {PT_VX, PT_VY, PT_VZ, PT_PT, PT_PF, PT_RX, PT_RY, PT_RZ, PT_PTO, PT_PFO,
+                               PT_SXX, PT_SYY, PT_SZZ, PT_SXY, PT_SXZ, PT_SYZ, PT_FOX, PT_FOY, PT_FOZ};
+    hipError_t e = hipSuccess;
+    for (int f : zero_fields)
+        for (int c = 0; c < (f < PT_NPING ? 2 : 1) && e == hipSuccess; ++c) e = launch_fill(g->f[f][c], 0.0, n, g->stream);
+    // coefficients before the first refresh (which overwrites them)
+    if (e == hipSuccess) e = launch_fill(g->f[PT_MN][0], p.mu0, n, g->stream);
+    if (e == hipSuccess) e = launch_fill(g->f[PT_KC][0], p.kmuf0, n, g->stream);
+    if (e == hipSuccess) e = launch_fill(g->f[PT_ETA][0], 1.0, n, g->stream);
+    if (e == hipSuccess) e = launch_fill(g->f[PT_MUS][0], p.mu0 * p.phi0 * p.cmu, n, g->stream);
+    if (e != hipSuccess) return hip_fail(g, e, "reset state");
+    // ln(1-phi) keeps its buffers: the present copy becomes copy 0 with the rest
+    if (g->cur[PT_LP] != 0) {
+        e = launch_copy(g->f[PT_LP][1], g->f[PT_LP][0], n, g->stream);
+        if (e != hipSuccess) return hip_fail(g, e, "reset state");
+    }
+    std::memset(g->cur, 0, sizeof(g->cur));
+    g->iter = 0;
+    g->ref_set = false;
+    g->refreshed = false;
+    g->norms_pending = false;
+    g->mws_clean = false;
+    g->mx_copy = 0;
+    return clear_domain(g);
+}
+
+pt_status pt_get_counters(const pt_grid* g, pt_counters* out) {
+    if (!g || !out) return PT_EINVAL;
+    std::memset(out, 0, sizeof(*out));
+    out->version = PT_ABI_VERSION;
+    out->iter = g->iter;
+    out->refreshed = g->refreshed ? 1 : 0;
+    out->ref_set = g->ref_set ? 1 : 0;
+    out->ref_v = g->ref_v;
+    out->ref_p = g->ref_p;
+    for (int f = 0; f < PT_NPING; ++f) out->cur[f] = g->cur[f];
+    out->mixed_copy = g->mx_copy;
+    out->mixed_clean = g->mws_clean ? 1 : 0;
+    return PT_OK;
+}
+
+pt_status pt_set_counters(pt_grid* g, const pt_counters* in) {
+    if (!g || !in) return PT_EINVAL;
+    if (in->version != PT_ABI_VERSION || in->iter < 0 || (in->mixed_copy & ~1) || (in->mixed_clean & ~1) ||
+        (in->refreshed & ~1) || (in->ref_set & ~1))
+        return fail(g, PT_EINVAL, "bad counters");
+    for (int f = 0; f < PT_NPING; ++f)
+        if (in->cur[f] & ~1) return fail(g, PT_EINVAL, "bad copy index in counters");
+    g->iter = in->iter;
+    g->refreshed = in->refreshed != 0;
+    g->ref_set = in->ref_set != 0;
+    g->ref_v = in->ref_v;
+    g->ref_p = in->ref_p;
+    for (int f = 0; f < PT_NPING; ++f) g->cur[f] = in->cur[f];
+    // the mixed workspace's contents count as kept only if it is bound
+    g->mx_copy = in->mixed_copy;
+    g->mws_clean = g->mws && in->mixed_clean != 0;
     return PT_OK;
 }
 
@@ -892,7 +1029,8 @@ pt_status pt_picard_step(pt_grid* g, int32_t update_history, int32_t n_picard, d
         if (st != PT_OK) return st;
         if (g->progress) g->progress(g->progress_user, PT_PROGRESS_STAGE, 0, p, it);
     }
-    return PT_OK;
+    // a porosity step that left (0, 1) would surface only at the next norm read
+    return read_domain(g);
 }
 
 pt_status pt_adjoint_workspace_size(const pt_grid* g, int32_t max_sensors, size_t* bytes) {
@@ -985,15 +1123,12 @@ template <typename Rec>
 pt_status recorded_step(pt_grid* g, int n, int32_t n_picard, double rtol, int64_t max_iter, Rec rec,
                         int64_t* fit, int32_t phase, bool mixed) {
     const int64_t box = mx_box(g);
+    // pt_begin_step restarts the FP32 damped residual of the mixed solves, so
+    // that a step recomputed from its checkpoint repeats the recorded one bit
+    // for bit
     pt_status st = pt_begin_step(g, n >= 1 ? 1 : 0);
     if (st != PT_OK) return st;
-    if (mixed) {
-        // the FP32 damped residual starts each step at zero, so that a step
-        // recomputed from its checkpoint repeats the recorded one bit for bit
-        hipError_t e = hipMemsetAsync(g->mws, 0, 16 * box * (int64_t)sizeof(float), g->stream);
-        if (e != hipSuccess) return hip_fail(g, e, "mixed step set-up");
-        g->mx_copy = 0;
-    }
+    (void)mixed;
     for (int p = 0; p < n_picard; ++p) {
         st = refresh_impl(g, 1.0, 1.0);
         if (st != PT_OK) return st;

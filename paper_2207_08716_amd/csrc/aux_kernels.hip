@@ -169,7 +169,28 @@ __global__ __launch_bounds__(AB) void k_porosity(Geom g, Coef c, AuxPtrs a) {
     if (k < g.nz - 1) adv += 0.5 * a.vz[at(g, i, j, k + 1)] * (sf(i, j, k + 1) - s) * c.dzi;
     const double pt = a.pt[o], pf = a.pf[o];
     const double dphidt = c.beta_phi * ((pf - a.pfo[o]) - (pt - a.pto[o])) * c.dti + (pf - pt) / a.eta[o] + adv;
-    a.lp_o[o] = a.lpo[o] - c.dt * dphidt;
+    const double lpn = a.lpo[o] - c.dt * dphidt;
+    a.lp_o[o] = lpn;
+    if (!(lpn < 0.0 && lpn > -1.0e300)) *a.domain = 1.0;   // phi outside (0, 1)
+}
+
+// ln(1-phi) (and its old value) from the porosity on the cells; the domain
+// flag is set where phi is not in (0, 1).
+__global__ __launch_bounds__(AB) void k_set_porosity(Geom g, const double* __restrict__ phi, double* __restrict__ lp,
+                                                     double* __restrict__ lpo, double* __restrict__ domain) {
+    Idx q;
+    if (!box_index(g, (int64_t)blockIdx.x * AB + threadIdx.x, q)) return;
+    if (q.i >= g.nx || q.j >= g.ny || q.k >= g.nz) return;
+    const int64_t o = at(g, q.i, q.j, q.k);
+    const double p = phi[o];
+    if (!(p > 0.0 && p < 1.0)) *domain = 1.0;
+    const double l = log(1.0 - p);
+    lp[o] = l;
+    lpo[o] = l;
+}
+
+__global__ __launch_bounds__(AB) void k_fill(double* __restrict__ dst, double v, int64_t n) {
+    for (int64_t t = (int64_t)blockIdx.x * AB + threadIdx.x; t < n; t += (int64_t)gridDim.x * AB) dst[t] = v;
 }
 
 // Streaming copy: each thread moves CU_UNROLL 16-byte vectors per pass, all
@@ -309,6 +330,21 @@ hipError_t launch_fo(const Geom& g, const Coef& c, const RefreshCoef& r, const A
 
 hipError_t launch_porosity_step(const Geom& g, const Coef& c, const AuxPtrs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_porosity, box_grid(g), dim3(AB), 0, s, g, c, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_porosity(const Geom& g, const double* phi, double* lp, double* lpo, double* domain,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(k_set_porosity, box_grid(g), dim3(AB), 0, s, g, phi, lp, lpo, domain);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(double* dst, double v, int64_t n, hipStream_t s) {
+    if (n > 0) {
+        int64_t blocks = (n + AB - 1) / AB;
+        if (blocks > 256 * 16) blocks = 256 * 16;
+        hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(AB), 0, s, dst, v, n);
+    }
     return hipGetLastError();
 }
 

@@ -427,7 +427,12 @@ __global__ __launch_bounds__((sweep_bx<T, MODE, NORMS>() * (HV ? HV : sweep_by<T
             } else {
                 p.pt_o[o] = ptn;
                 p.pf_o[o] = pfn;
-                if (UPD_LP) p.lp_o[o] = lpn;
+                if constexpr (UPD_LP) {
+                    p.lp_o[o] = lpn;
+                    // phi' outside (0, 1): ln(1-phi)' not in (-inf, 0); checked
+                    // with the norms (the plain sweep has no register to spare)
+                    if (NORMS && !(lpn < zero && lpn > T(-1.0e300))) *p.domain = 1.0;
+                }
             }
             if (WNORM) {
                 nm[1] = nanmax(nm[1], T(fabs(rpt_k)));

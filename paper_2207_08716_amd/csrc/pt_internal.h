@@ -10,12 +10,16 @@
 
 namespace ptk {
 
+// Compute units assumed when the device cannot be queried (MI355X: 256).
+constexpr int DEFAULT_CUS = 256;
+
 // Index layout common to every field: (k * (ny+1) + j) * P + i.
 struct Geom {
     int nx, ny, nz;
     int64_t P;   // row pitch (elements)
     int64_t S;   // plane pitch = (ny + 1) * P
     int kz;      // planes per z chunk of a sweep (set per sweep variant at launch)
+    int cus = DEFAULT_CUS;   // compute units of the device (one sweep block each)
 };
 
 // Physical and numerical constants, in the form the kernels use them.
@@ -55,6 +59,7 @@ struct SweepPtrs {
     T *vx_o, *vy_o, *vz_o, *pt_o, *pf_o, *lp_o, *rx_o, *ry_o, *rz_o;
     float *res_fx, *res_fy, *res_fz, *res_rpt, *res_rpf;   // residual mode outputs
     double* partials;              // [n_blocks][8] maxima (norm variants)
+    double* domain;                // set to 1 where ln(1-phi)' leaves (-inf, 0) (thesis mode)
 };
 
 constexpr int NNORM = 8;
@@ -81,14 +86,13 @@ constexpr int BY_NORMS = 7;
 constexpr int KZ_MAX = 256;
 
 constexpr int KZ_MIN = 4;
-constexpr int64_t GPU_CUS = 256;   // MI355X compute units (one sweep block each)
 
 inline int64_t tiles_xy(const Geom& g, int bx = BX, int by = BY) {
     return (int64_t)((g.nx + bx - 3) / (bx - 2)) * ((g.ny + by - 3) / (by - 2));
 }
 
 // Planes per z chunk for a tiling: the sweep blocks occupy one CU each, so a
-// launch takes ceil(blocks / 256) rounds of (chunk + 2) plane steps (two
+// launch takes ceil(blocks / CUs) rounds of (chunk + 2) plane steps (two
 // planes of halo and prefetch per chunk); the chunk minimising that wins,
 // the longer one on ties.
 inline int choose_kz(const Geom& g, int bx, int by, int64_t* cost_out = nullptr) {
@@ -97,7 +101,8 @@ inline int choose_kz(const Geom& g, int bx, int by, int64_t* cost_out = nullptr)
     int64_t best_cost = -1;
     for (int kz = KZ_MAX; kz >= KZ_MIN; kz /= 2) {
         const int64_t blocks = t * ((g.nz + kz - 1) / kz);
-        const int64_t cost = ((blocks + GPU_CUS - 1) / GPU_CUS) * (std::min(kz, g.nz) + 2);
+        const int64_t cus = g.cus > 0 ? g.cus : DEFAULT_CUS;
+        const int64_t cost = ((blocks + cus - 1) / cus) * (std::min(kz, g.nz) + 2);
         if (best_cost < 0 || cost < best_cost) {
             best = kz;
             best_cost = cost;
@@ -189,6 +194,7 @@ struct AuxPtrs {
     double *mn, *kc, *eta, *mus;
     const double* k0;
     double* lp_o;                  // porosity step output
+    double* domain;                // set to 1 where ln(1-phi) leaves (-inf, 0)
 };
 
 struct RefreshCoef {
@@ -209,6 +215,12 @@ hipError_t launch_fo(const Geom& g, const Coef& c, const RefreshCoef& r, const A
                      hipStream_t s);
 hipError_t launch_porosity_step(const Geom& g, const Coef& c, const AuxPtrs& a, hipStream_t s);
 hipError_t launch_copy(const double* src, double* dst, int64_t n, hipStream_t s);
+// ln(1-phi) and its old value from a porosity field; domain <- 1 where phi is
+// not in (0, 1).
+hipError_t launch_set_porosity(const Geom& g, const double* phi, double* lp, double* lpo, double* domain,
+                               hipStream_t s);
+// n doubles <- v (a kernel, so that the clear can sit in a captured graph).
+hipError_t launch_fill(double* dst, double v, int64_t n, hipStream_t s);
 
 // Mixed precision helpers.
 struct MixedPtrs {

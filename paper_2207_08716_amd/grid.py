@@ -55,31 +55,66 @@ class Grid:
             raise ValueError("the solver runs on the GPU only")
         self.pitch = pitch or ((nx + 1 + 31) // 32) * 32
         self.k0field = bool(k0field)
-        h = C.c_void_p()
         self._params = abi.params_from(phys, self.k0field)
-        st = self.lib.pt_create(nx, ny, nz, self.pitch, C.byref(self._params), C.byref(h))
-        if st != 0:
-            raise abi.PTError(st, "pt_create rejected the grid or parameters")
-        self.h = h
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        _check(self.lib, h, self.lib.pt_set_stream(h, C.c_void_p(self.stream.cuda_stream)), "set_stream")
+        self.h = None
+        self._create_handle()
         box = (nz + 1, ny + 1, self.pitch)
-        assert self.lib.pt_field_elems(h) == box[0] * box[1] * box[2]
+        assert self.lib.pt_field_elems(self.h) == box[0] * box[1] * box[2]
         self.buf = {}
         with torch.cuda.stream(self.stream):
             for fid, name in enumerate(abi.FIELDS):
                 if name == "k0" and not self.k0field:
                     continue
                 ncopy = 2 if fid < abi.NPING else 1
-                self.buf[name] = []
-                for cp in range(ncopy):
-                    t = torch.zeros(box, dtype=torch.float64, device=self.device)
-                    self.buf[name].append(t)
-                    _check(self.lib, h, self.lib.pt_bind_field(h, fid, cp, C.c_void_p(t.data_ptr())), f"bind {name}")
+                self.buf[name] = [torch.zeros(box, dtype=torch.float64, device=self.device) for _ in range(ncopy)]
             nbytes = C.c_size_t()
-            _check(self.lib, h, self.lib.pt_workspace_size(h, C.byref(nbytes)), "workspace_size")
+            _check(self.lib, self.h, self.lib.pt_workspace_size(self.h, C.byref(nbytes)), "workspace_size")
             self.ws = torch.zeros((nbytes.value + 7) // 8, dtype=torch.float64, device=self.device)
-            _check(self.lib, h, self.lib.pt_bind_workspace(h, C.c_void_p(self.ws.data_ptr()), nbytes.value), "bind ws")
+            self.ws_bytes = nbytes.value
+        self._bind_all()
+
+    def _create_handle(self):
+        h = C.c_void_p()
+        st = self.lib.pt_create(self.nx, self.ny, self.nz, self.pitch, C.byref(self._params), C.byref(h))
+        if st != 0:
+            raise abi.PTError(st, "pt_create rejected the grid or parameters")
+        self.h = h
+        _check(self.lib, h, self.lib.pt_set_stream(h, C.c_void_p(self.stream.cuda_stream)), "set_stream")
+
+    def _bind_all(self):
+        h = self.h
+        for name, bufs in self.buf.items():
+            fid = abi.FIELD_ID[name]
+            for cp, t in enumerate(bufs):
+                _check(self.lib, h, self.lib.pt_bind_field(h, fid, cp, C.c_void_p(t.data_ptr())), f"bind {name}")
+        _check(self.lib, h, self.lib.pt_bind_workspace(h, C.c_void_p(self.ws.data_ptr()), self.ws_bytes), "bind ws")
+        if getattr(self, "mws", None) is not None:
+            _check(self.lib, h, self.lib.pt_bind_mixed_workspace(h, C.c_void_p(self.mws.data_ptr()),
+                                                                 self.mws_bytes), "bind mixed")
+        if getattr(self, "aws", None) is not None:
+            _check(self.lib, h, self.lib.pt_bind_adjoint_workspace(h, C.c_void_p(self.aws.data_ptr()),
+                                                                   self.aws_bytes, int(self.aws_sensors)),
+                   "bind adjoint")
+
+    # ---- resuming on a new handle ----------------------------------------------
+    def counters(self) -> abi.Counters:
+        c = abi.Counters()
+        _check(self.lib, self.h, self.lib.pt_get_counters(self.h, C.byref(c)), "get_counters")
+        return c
+
+    def set_counters(self, c: abi.Counters):
+        _check(self.lib, self.h, self.lib.pt_set_counters(self.h, C.byref(c)), "set_counters")
+
+    def recreate_handle(self):
+        """Destroy the C handle and create a new one on the same buffers,
+        carrying the counters over (the run continues bit for bit)."""
+        c = self.counters()
+        self.lib.pt_destroy(self.h)
+        self.h = None
+        self._create_handle()
+        self._bind_all()
+        self.set_counters(c)
 
     def close(self):
         if getattr(self, "h", None):
@@ -123,23 +158,16 @@ class Grid:
                 v.copy_(torch.from_numpy(a).to(self.device, non_blocking=False))
 
     def load_initial(self, phi, k0=None):
-        """Initial state of every workload: V = R = 0, pressures 0, stress
-        history 0, ln(1-phi) from phi, Mn = mu0; coefficients take their
-        background values until the first refresh."""
-        ph = self.phys
-        lp = np.log(1.0 - np.asarray(phi, dtype=np.float64))
-        self.set("lp", lp)
-        self.set("lpo", lp)
-        self.set("mn", ph.mu0)
-        self.set("eta", 1.0)
-        self.set("mus", ph.mu0 * ph.phi0 * ph.cmu)
-        self.set("kc", ph.kmuf0)
+        """Initial state of every workload (pt_reset_state, pt_set_porosity):
+        V = R = 0, pressures 0, stress history 0, ln(1-phi) from phi, Mn = mu0;
+        coefficients take their background values until the first refresh."""
         if self.k0field:
             if k0 is None:
                 raise ValueError("k0 field expected")
             self.set("k0", k0)
         elif k0 is not None:
             raise ValueError("grid created without a k0 field")
+        self.reset_state(phi)
 
     # ---- solver entry points --------------------------------------------------
     def begin_step(self, update_history=False):
@@ -203,6 +231,7 @@ class Grid:
         _check(self.lib, self.h, self.lib.pt_mixed_workspace_size(self.h, C.byref(nbytes)), "mixed size")
         with torch.cuda.stream(self.stream):
             self.mws = torch.zeros((nbytes.value + 3) // 4, dtype=torch.float32, device=self.device)
+        self.mws_bytes = nbytes.value
         _check(self.lib, self.h, self.lib.pt_bind_mixed_workspace(self.h, C.c_void_p(self.mws.data_ptr()),
                                                                   nbytes.value), "bind mixed")
 
@@ -245,6 +274,7 @@ class Grid:
         with torch.cuda.stream(self.stream):
             self.aws = torch.zeros((nbytes.value + 7) // 8, dtype=torch.float64, device=self.device)
             self.grad_buf = torch.zeros(self.buf["pt"][0].shape, dtype=torch.float64, device=self.device)
+        self.aws_bytes = nbytes.value
         _check(self.lib, self.h, self.lib.pt_bind_adjoint_workspace(self.h, C.c_void_p(self.aws.data_ptr()),
                                                                     nbytes.value, int(max_sensors)), "bind adjoint")
         self.aws_sensors = max_sensors
@@ -332,19 +362,19 @@ class Grid:
         return J.value, self.grad_buf[:self.nz, :self.ny, :self.nx], fit.value, ait.value
 
     def reset_state(self, phi):
-        """Back to the initial state of every workload (V = R = 0, pressures
-        and stress history 0, ln(1-phi) from phi, Mn = mu0), keeping k0."""
-        for name in ("vx", "vy", "vz", "pt", "pf", "rx", "ry", "rz", "pto", "pfo",
-                     "sxx", "syy", "szz", "sxy", "sxz", "syz", "fox", "foy", "foz"):
-            self.set(name, 0.0)
-        ph = self.phys
-        lp = np.log(1.0 - np.asarray(phi, dtype=np.float64))
-        self.set("lp", lp)
-        self.set("lpo", lp)
-        self.set("mn", ph.mu0)
-        self.set("eta", 1.0)
-        self.set("mus", ph.mu0 * ph.phi0 * ph.cmu)
-        self.set("kc", ph.kmuf0)
+        """Back to the initial state of every workload (pt_reset_state: V = R
+        = 0, pressures and stress history 0, Mn = mu0, counters cleared),
+        then ln(1-phi) from phi (pt_set_porosity), keeping k0."""
+        _check(self.lib, self.h, self.lib.pt_reset_state(self.h), "reset_state")
+        self.set_porosity(phi)
+
+    def set_porosity(self, phi):
+        """ln(1-phi) and its old value from a porosity array (nz, ny, nx) or
+        device tensor (pt_set_porosity; PTError PT_EDOMAIN if phi leaves (0, 1))."""
+        with torch.cuda.stream(self.stream):
+            box = torch.zeros(self.buf["pt"][0].shape, dtype=torch.float64, device=self.device)
+            box[:self.nz, :self.ny, :self.nx].copy_(torch.as_tensor(phi, dtype=torch.float64, device=self.device))
+        _check(self.lib, self.h, self.lib.pt_set_porosity(self.h, C.c_void_p(box.data_ptr())), "set_porosity")
 
     def copy(self, src: torch.Tensor, dst: torch.Tensor):
         assert src.dtype == dst.dtype == torch.float64 and src.numel() == dst.numel()

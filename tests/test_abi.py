@@ -98,5 +98,46 @@ def test_driver_and_adjoint_entry_points_validate_on_the_host(lib):
         assert lib.pt_adjoint_run(h, 1, 1, 0, 1e-8, 1e-8, 100, sensors, 2, d_obs, C.c_void_p(0x1000), 1 << 20,
                                   C.c_void_p(0x1000), C.byref(J), C.byref(fit), C.byref(ait)) == -1
         assert lib.pt_set_progress(h, abi.PROGRESS_FN(), None) == 0
+        # state set-up refuses an unbound grid
+        assert lib.pt_reset_state(h) == -1
+        assert lib.pt_set_porosity(h, C.c_void_p(0x1000)) == -1
+        assert lib.pt_set_porosity(h, C.c_void_p(0x1008)) == -1
     finally:
         lib.pt_destroy(h)
+
+
+def test_counters_round_trip_on_the_host(lib):
+    """pt_get_counters / pt_set_counters carry the host-side state of a handle
+    to another one (no device call)."""
+    p = abi.params_from(inputs.Physics(), False)
+    h1, h2 = C.c_void_p(), C.c_void_p()
+    assert lib.pt_create(6, 5, 4, 32, C.byref(p), C.byref(h1)) == 0
+    assert lib.pt_create(6, 5, 4, 32, C.byref(p), C.byref(h2)) == 0
+    try:
+        c = abi.Counters()
+        assert lib.pt_get_counters(h1, C.byref(c)) == 0
+        assert c.version == abi.ABI_VERSION and c.iter == 0 and c.ref_set == 0 and list(c.cur) == [0] * abi.NPING
+        c.iter, c.refreshed, c.ref_set, c.ref_v, c.ref_p = 37, 1, 1, 2.5, 0.125
+        c.cur[0], c.cur[5], c.mixed_copy = 1, 1, 1
+        assert lib.pt_set_counters(h2, C.byref(c)) == 0
+        d = abi.Counters()
+        assert lib.pt_get_counters(h2, C.byref(d)) == 0
+        assert (d.iter, d.refreshed, d.ref_set, d.ref_v, d.ref_p) == (37, 1, 1, 2.5, 0.125)
+        assert list(d.cur) == [1, 0, 0, 0, 0, 1, 0, 0, 0] and d.mixed_copy == 1
+        assert d.mixed_clean == 0                       # no mixed workspace bound
+        gv, gp = C.c_double(), C.c_double()
+        assert lib.pt_residual_reference(h2, C.byref(gv), C.byref(gp)) == 0 and (gv.value, gp.value) == (2.5, 0.125)
+        cur = C.c_int32()
+        assert lib.pt_current(h2, 5, C.byref(cur)) == 0 and cur.value == 1
+        for field, value in (("version", 99), ("iter", -1), ("mixed_copy", 2)):
+            bad = abi.Counters()
+            C.memmove(C.byref(bad), C.byref(c), C.sizeof(c))
+            setattr(bad, field, value)
+            assert lib.pt_set_counters(h2, C.byref(bad)) == -1, field
+        bad = abi.Counters()
+        C.memmove(C.byref(bad), C.byref(c), C.sizeof(c))
+        bad.cur[3] = 2
+        assert lib.pt_set_counters(h2, C.byref(bad)) == -1
+    finally:
+        lib.pt_destroy(h1)
+        lib.pt_destroy(h2)

@@ -104,3 +104,33 @@ def test_autograd_function():
     fd = (Jp - Jm) / (2 * h)
     dd = float((grad * v).sum())
     assert abs(dd - fd) <= 1e-6 * abs(fd), (dd, fd)
+
+
+def test_autograd_backward_after_a_second_forward():
+    """The gradient of a forward survives a later forward on the same problem
+    (gradcheck, finite-difference probes and several losses do that)."""
+    import torch
+    from paper_2207_08716_amd import autograd as ag
+    from paper_2207_08716_amd import grid
+    n = 10
+    cfg, phi, logk0, sensors = _problem(n, seed=9, ns=8)
+    g = grid.Grid(cfg.phys, n, n, n, k0field=True)
+    g.load_initial(phi, np.exp(logk0))
+    prob = ag.StageProblem(g, phi, sensors, np.zeros(len(sensors)), rtol=1e-13)
+    rng = np.random.default_rng(4)
+    v = rng.standard_normal(logk0.shape)
+    m_a = torch.tensor(logk0, dtype=torch.float64, device="cuda", requires_grad=True)
+    J_a = ag.LogKMisfit.apply(m_a, prob)
+    m_b = torch.tensor(logk0 + 0.3 * v, dtype=torch.float64, device="cuda", requires_grad=True)
+    J_b = ag.LogKMisfit.apply(m_b, prob)
+    assert abs(J_a.item() - J_b.item()) > 1e-6 * abs(J_a.item())
+    J_a.backward()
+    grad = m_a.grad.detach().cpu().numpy()
+    h = 1e-5
+    with torch.no_grad():
+        vt = torch.tensor(v, device="cuda")
+        Jp = ag.LogKMisfit.apply(m_a + h * vt, prob).item()
+        Jm = ag.LogKMisfit.apply(m_a - h * vt, prob).item()
+    fd = (Jp - Jm) / (2 * h)
+    dd = float((grad * v).sum())
+    assert abs(dd - fd) <= 1e-6 * abs(fd), (dd, fd)
