@@ -223,6 +223,22 @@ pt_status pt_last_norms(pt_grid* g, pt_norms* out);
 pt_status pt_solve_linear(pt_grid* g, double rtol, int64_t max_iter,
                           int64_t* iters, double* rho);
 
+/* pt_solve_linear for callers that cannot allocate or bind device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same solve, bit for bit, with the per-block maxima, the
+ * reduced norms and the domain flag in a static device scratch of the
+ * library (1 MiB per GPU, a file-scope array kept until the process ends)
+ * instead of the bound workspace, which it does not need.  The caller still
+ * binds every field.  The device current at the call must hold the grid's
+ * buffers.  Grids with more than 16382 norm blocks (about 1100^3 cells) are
+ * refused with PT_EINVAL before any launch.  Calls on one GPU share its
+ * scratch: calls that overlap on one GPU (other threads, other streams)
+ * race.  Allocates nothing (no hipMalloc, no library allocation);
+ * synchronises; the norms of its last check are not readable afterwards
+ * (pt_last_norms reports none). */
+pt_status pt_solve_linear_static(pt_grid* g, double rtol, int64_t max_iter,
+                                 int64_t* iters, double* rho);
+
 /* The residual reference of the current step (both -1 if not yet set), and
  * setting it explicitly (negative values unset it). */
 pt_status pt_residual_reference(const pt_grid* g, double* gv, double* gp);

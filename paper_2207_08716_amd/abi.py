@@ -51,7 +51,7 @@ class Counters(C.Structure):
 
 EXPORTS = ["pt_create", "pt_destroy", "pt_field_elems", "pt_bind_field", "pt_workspace_size",
            "pt_bind_workspace", "pt_set_stream", "pt_set_progress", "pt_set_params", "pt_current", "pt_begin_step",
-           "pt_refresh", "pt_iteration", "pt_iterate", "pt_last_norms", "pt_solve_linear",
+           "pt_refresh", "pt_iteration", "pt_iterate", "pt_last_norms", "pt_solve_linear", "pt_solve_linear_static",
            "pt_residual_reference", "pt_set_residual_reference",
            "pt_porosity_step", "pt_reset_state", "pt_set_porosity", "pt_get_counters", "pt_set_counters",
            "pt_picard_step", "pt_mixed_workspace_size", "pt_bind_mixed_workspace", "pt_residual",
@@ -77,6 +77,10 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"HIP library not built: {path} (run __graft_entry__.build())")
+    # torch first: the library must bind the HIP runtime torch loaded (torch
+    # owns the memory and the streams); loaded first, it would map a second
+    # runtime, and torch's own would then find no GPU
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     P = C.POINTER
     vp = C.c_void_p
@@ -97,6 +101,7 @@ def load(path: str = LIB_PATH):
     lib.pt_iterate.argtypes = [vp, C.c_int64]
     lib.pt_last_norms.argtypes = [vp, P(Norms)]
     lib.pt_solve_linear.argtypes = [vp, C.c_double, C.c_int64, P(C.c_int64), P(C.c_double)]
+    lib.pt_solve_linear_static.argtypes = [vp, C.c_double, C.c_int64, P(C.c_int64), P(C.c_double)]
     lib.pt_porosity_step.argtypes = [vp]
     lib.pt_reset_state.argtypes = [vp]
     lib.pt_set_porosity.argtypes = [vp, vp]

@@ -4,6 +4,7 @@
 #include <cstring>
 #include <new>
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -33,6 +34,7 @@ struct pt_grid {
     bool refreshed = false;    // any refresh done on this handle
     bool norms_pending = false;
     bool broken = false;       // PT_ESTATE: a divergence, domain or device error occurred
+    double* nw = nullptr;      // norm area in place of the workspace (pt_solve_linear_static)
     pt_progress_fn progress = nullptr;   // per-stage report of long calls
     void* progress_user = nullptr;
     std::string err;
@@ -129,6 +131,12 @@ RefreshCoef make_refresh(const pt_grid* g, double r_eta, double r_mu) {
 size_t ws_needed(const pt_grid* g);
 double* domain_flag(pt_grid* g);
 
+// Where the sweeps put their per-block maxima, the reduced norms and the
+// domain flag: the bound workspace, or the static scratch during
+// pt_solve_linear_static.
+double* norm_area(pt_grid* g) { return g->nw ? g->nw : static_cast<double*>(g->ws); }
+bool norm_area_ready(const pt_grid* g) { return g->nw || (g->ws && g->ws_bytes >= ws_needed(g)); }
+
 double* cur(pt_grid* g, int f) { return f < PT_NPING ? g->f[f][g->cur[f]] : g->f[f][0]; }
 double* alt(pt_grid* g, int f) { return g->f[f][1 - g->cur[f]]; }
 
@@ -184,7 +192,7 @@ pt_status check_ready(pt_grid* g) {
     }
     if (!bound(g, kAllCore, true)) return fail(g, PT_EINVAL, "not every field (both copies of the iterated ones) is bound");
     if ((g->prm.flags & PT_F_K0FIELD) && !g->f[PT_K0][0]) return fail(g, PT_EINVAL, "PT_F_K0FIELD set but PT_K0 not bound");
-    if (!g->ws || g->ws_bytes < ws_needed(g)) return fail(g, PT_EINVAL, "workspace not bound or too small");
+    if (!norm_area_ready(g)) return fail(g, PT_EINVAL, "workspace not bound or too small");
     return PT_OK;
 }
 
@@ -197,7 +205,8 @@ size_t ws_needed(const pt_grid* g) {
 }
 
 double* domain_flag(pt_grid* g) {
-    return g->ws ? static_cast<double*>(g->ws) + norm_blocks(g->geom) * NNORM + NNORM : nullptr;
+    double* a = norm_area(g);
+    return a ? a + norm_blocks(g->geom) * NNORM + NNORM : nullptr;
 }
 
 pt_status clear_domain(pt_grid* g) {
@@ -228,15 +237,15 @@ SweepPtrs<double> sweep_ptrs(pt_grid* g) {
     p.vx_o = alt(g, PT_VX); p.vy_o = alt(g, PT_VY); p.vz_o = alt(g, PT_VZ);
     p.pt_o = alt(g, PT_PT); p.pf_o = alt(g, PT_PF); p.lp_o = alt(g, PT_LP);
     p.rx_o = alt(g, PT_RX); p.ry_o = alt(g, PT_RY); p.rz_o = alt(g, PT_RZ);
-    p.partials = static_cast<double*>(g->ws);
+    p.partials = norm_area(g);
     p.domain = domain_flag(g);
     return p;
 }
 
 pt_status reduce_norms(pt_grid* g) {
     const int64_t nb = norm_blocks(g->geom);
-    double* out = static_cast<double*>(g->ws) + nb * NNORM;
-    hipError_t e = launch_reduce_max(static_cast<double*>(g->ws), nb, out, g->stream);
+    double* out = norm_area(g) + nb * NNORM;
+    hipError_t e = launch_reduce_max(norm_area(g), nb, out, g->stream);
     if (e != hipSuccess) return hip_fail(g, e, "reduce");
     g->norms_pending = true;
     return PT_OK;
@@ -272,7 +281,7 @@ float* mx(pt_grid* g, int b) { return g->mws + (int64_t)b * mx_box(g); }
 // The eight reduced norms and the domain flag (copied together).
 pt_status read_norms(pt_grid* g, pt_norms* out) {
     double host[NNORM + 1];
-    hipError_t e = hipMemcpyAsync(host, static_cast<double*>(g->ws) + norm_blocks(g->geom) * NNORM, sizeof(host),
+    hipError_t e = hipMemcpyAsync(host, norm_area(g) + norm_blocks(g->geom) * NNORM, sizeof(host),
                                   hipMemcpyDeviceToHost, g->stream);
     const hipError_t es = hipStreamSynchronize(g->stream);   // also on a failed copy: host is local
     if (e == hipSuccess) e = es;
@@ -460,7 +469,7 @@ pt_status pt_iteration(pt_grid* g, int32_t update_porosity, int32_t want_norms) 
     if (!g) return PT_EINVAL;
     pt_status st = check_ready(g);
     if (st != PT_OK) return st;
-    if (want_norms && (!g->ws || g->ws_bytes < ws_needed(g))) return fail(g, PT_EINVAL, "norms need a bound workspace");
+    if (want_norms && !norm_area_ready(g)) return fail(g, PT_EINVAL, "norms need a bound workspace");
     return iteration_impl(g, update_porosity ? 1 : 0, want_norms ? 1 : 0);
 }
 
@@ -488,11 +497,13 @@ pt_status pt_last_norms(pt_grid* g, pt_norms* out) {
     return read_norms(g, out);
 }
 
-pt_status pt_solve_linear(pt_grid* g, double rtol, int64_t max_iter, int64_t* iters, double* rho) {
-    if (!g || !(rtol > 0.0) || max_iter < 1) return PT_EINVAL;
+}  // extern "C"
+
+namespace {
+// The linear solve of pt_solve_linear on whatever norm area is in force.
+pt_status solve_linear_core(pt_grid* g, double rtol, int64_t max_iter, int64_t* iters, double* rho) {
     pt_status st = check_ready(g);
     if (st != PT_OK) return st;
-    if (!g->ws || g->ws_bytes < ws_needed(g)) return fail(g, PT_EINVAL, "workspace not bound");
     const int64_t nup = g->prm.nup;
     double r = INFINITY;
     int64_t it = 0;
@@ -522,6 +533,65 @@ pt_status pt_solve_linear(pt_grid* g, double rtol, int64_t max_iter, int64_t* it
     if (iters) *iters = it;
     if (rho) *rho = r;
     return (r <= rtol) ? PT_OK : PT_ENOTCONV;
+}
+
+// ---- the static scratch of pt_solve_linear_static -------------------------
+// File-scope device array: each GPU the library runs on holds its own copy
+// until the process ends.  Host code never passes the array's name to a
+// kernel (on the host it is a stand-in, not a device address): the address
+// is looked up once per device with hipGetSymbolAddress, with that device
+// current, and kept here.
+constexpr int64_t STATIC_SCRATCH_DOUBLES = 131072;   // 1 MiB
+__device__ __align__(256) double scratch[STATIC_SCRATCH_DOUBLES];
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mutex;
+double* scratch_ptr[MAX_DEVICES] = {};
+
+pt_status static_scratch(pt_grid* g, double** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(g, e, "static scratch: current device");
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(g, PT_EINVAL, "static scratch: device index out of range");
+    std::lock_guard<std::mutex> lock(scratch_mutex);
+    if (!scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_fail(g, e != hipSuccess ? e : hipErrorInvalidSymbol, "static scratch: symbol address");
+        scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = scratch_ptr[dev];
+    return PT_OK;
+}
+}  // namespace
+
+extern "C" {
+
+pt_status pt_solve_linear(pt_grid* g, double rtol, int64_t max_iter, int64_t* iters, double* rho) {
+    if (!g || !(rtol > 0.0) || max_iter < 1) return PT_EINVAL;
+    if (!g->ws || g->ws_bytes < ws_needed(g)) return fail(g, PT_EINVAL, "workspace not bound");
+    return solve_linear_core(g, rtol, max_iter, iters, rho);
+}
+
+pt_status pt_solve_linear_static(pt_grid* g, double rtol, int64_t max_iter, int64_t* iters, double* rho) {
+    if (!g || !(rtol > 0.0) || max_iter < 1) return PT_EINVAL;
+    const int64_t need = norm_blocks(g->geom) * NNORM + NNORM + 1;
+    if (need > STATIC_SCRATCH_DOUBLES)
+        return fail(g, PT_EINVAL, "grid too large for the static scratch of pt_solve_linear_static "
+                                  "(more than 16382 norm blocks); use pt_solve_linear with a bound workspace");
+    double* sp = nullptr;
+    pt_status st = static_scratch(g, &sp);
+    if (st != PT_OK) return st;
+    g->nw = sp;
+    // the domain flag must start at zero (the linear sweep never sets it);
+    // a fill kernel, so that the call can sit in a captured graph
+    hipError_t e = launch_fill(domain_flag(g), 0.0, 1, g->stream);
+    if (e != hipSuccess) st = hip_fail(g, e, "static scratch clear");
+    if (st == PT_OK) st = solve_linear_core(g, rtol, max_iter, iters, rho);
+    // the norms of the last check stay readable only until the next call
+    // that computes norms into the bound workspace
+    g->nw = nullptr;
+    g->norms_pending = false;
+    return st;
 }
 
 pt_status pt_porosity_step(pt_grid* g) {
@@ -663,7 +733,7 @@ pt_status correction_sweep(pt_grid* g, int cp, int norms) {
     p.fox = mx(g, MX_RES + 0); p.foy = mx(g, MX_RES + 1); p.foz = mx(g, MX_RES + 2);
     p.pto = mx(g, MX_RES + 3); p.pfo = mx(g, MX_RES + 4);
     p.kc = mx(g, 21); p.mus = mx(g, 22); p.eta = mx(g, 23);
-    p.partials = static_cast<double*>(g->ws);
+    p.partials = norm_area(g);
     hipError_t e = launch_correction(g->geom, g->coef, p, norms, g->stream);
     if (e != hipSuccess) return hip_fail(g, e, "correction sweep");
     if (norms) return reduce_norms(g);
@@ -726,7 +796,7 @@ pt_status mixed_core(pt_grid* g, const MixedTarget& t, double rtol, double eta_i
     rp.res_fz = mx(g, MX_RES + 2);
     rp.res_rpt = mx(g, MX_RES + 3);
     rp.res_rpf = mx(g, MX_RES + 4);
-    rp.partials = static_cast<double*>(g->ws);
+    rp.partials = norm_area(g);
     const int64_t nup = g->prm.nup;
     // the inner solve stops when its residual has not reached a new minimum
     // (by 1 %) for this many checks: FP32 cannot go below its round-off level
@@ -914,7 +984,7 @@ pt_status transposed_solve(pt_grid* g, const double* kc, const double* mus, doub
     if (e != hipSuccess) return hip_fail(g, e, "adjoint clear");
     const int64_t nb = norm_blocks(g->geom);
     const double* rhs[5] = {ad(g, AD_RHS), ad(g, AD_RHS + 1), ad(g, AD_RHS + 2), ad(g, AD_RHS + 3), ad(g, AD_RHS + 4)};
-    e = launch_absmax5(g->geom, rhs, static_cast<double*>(g->ws), nb, g->stream);
+    e = launch_absmax5(g->geom, rhs, norm_area(g), nb, g->stream);
     if (e != hipSuccess) return hip_fail(g, e, "rhs norm");
     pt_status st = reduce_norms(g);
     if (st != PT_OK) return st;
@@ -942,7 +1012,7 @@ pt_status transposed_solve(pt_grid* g, const double* kc, const double* mus, doub
             p.fox = ad(g, AD_RHS); p.foy = ad(g, AD_RHS + 1); p.foz = ad(g, AD_RHS + 2);
             p.pto = ad(g, AD_RHS + 3); p.pfo = ad(g, AD_RHS + 4);
             p.eta = ad(g, AD_CHI); p.kc = kc; p.mus = mus;
-            p.partials = static_cast<double*>(g->ws);
+            p.partials = norm_area(g);
             e = launch_correction64(g->geom, g->coef, p, chk ? 1 : 0, g->stream);
             if (e != hipSuccess) return hip_fail(g, e, "adjoint sweep");
             cp ^= 1;

@@ -196,6 +196,16 @@ class Grid:
                                                                  C.byref(it), C.byref(rho)), "solve_linear")
         return it.value, rho.value, st == 0
 
+    def solve_linear_static(self, rtol, max_iter=1_000_000):
+        """pt_solve_linear_static: the same solve with the library's static
+        device scratch in place of the workspace (allocates nothing)."""
+        it = C.c_int64()
+        rho = C.c_double()
+        st = _check(self.lib, self.h, self.lib.pt_solve_linear_static(self.h, float(rtol), int(max_iter),
+                                                                        C.byref(it), C.byref(rho)),
+                    "solve_linear_static")
+        return it.value, rho.value, st == 0
+
     def residual_reference(self):
         gv = C.c_double()
         gp = C.c_double()
