@@ -262,9 +262,10 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=10, help="timed refresh cycles (15 PT iterations each)")
     ap.add_argument("--warmup", type=int, default=2, help="untimed refresh cycles before timing")
     ap.add_argument("--n", type=int, default=511)
-    ap.add_argument("--workload", choices=("anomaly", "waves"), default="anomaly",
+    ap.add_argument("--workload", choices=("anomaly", "waves", "production"), default="anomaly",
                     help="anomaly: two Gaussian anomalies on the unit cube (default); waves: the "
-                         "porosity-wave domain (30^3, three sources, dt 5e-4)")
+                         "porosity-wave domain (30^3, three sources, dt 5e-4); production: the "
+                         "sheared 30 x 30 x 60 box of Table 2 on n x n x 2n cells")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--ttt-n", type=int, default=127,
                     help="grid size of the mixed-vs-FP64 time-to-tolerance comparison (0: skip)")
@@ -291,7 +292,12 @@ def main(argv=None):
         return 1
 
     n = args.n
-    cfg = inputs.config_mixed(n) if args.workload == "anomaly" else inputs.config_waves(n)
+    if args.workload == "anomaly":
+        cfg = inputs.config_mixed(n)
+    elif args.workload == "waves":
+        cfg = inputs.config_waves(n)
+    else:
+        cfg = inputs.config_production(n, n, 2 * n)
     fields = inputs.initial_fields(cfg)
     g = schedules.make_grid(cfg, fields)
     s = g.stream
@@ -344,6 +350,22 @@ def main(argv=None):
 
     achieved = a_eff / t_sweep / 1e9
     traffic = measured_traffic(n) if args.workload == "anomaly" else None
+    # decompaction-switch flips (cells with |Pf - Pt| below 1e-12 of the
+    # largest pressure) and the share of cells whose viscosity the cap or the
+    # power law lowered, at the end of the timed run
+    pt_h, pf_h, mn_h = (g.view(k).cpu() for k in ("pt", "pf", "mn"))
+    pscale = max(float(pt_h.abs().max()), float(pf_h.abs().max()), 1e-300)
+    flips = int(((pf_h - pt_h).abs() < 1e-12 * pscale).sum())
+    weakened = float((mn_h < cfg.phys.mu0 * (1 - 1e-12)).double().mean())
+    del pt_h, pf_h, mn_h
+    workloads = {
+        "anomaly": (f"{n}^3 two-anomaly porosity grid, lognormal k0 (sigma 0.5), "
+                    "Drucker-Prager cap C=1 30deg, thesis PT schedule (refresh/norms every 15)"),
+        "waves": (f"{n}^3 porosity-wave domain (L=30, three sources of width 1), scalar k0, "
+                  "Drucker-Prager cap, dt 5e-4, thesis PT schedule (refresh/norms every 15)"),
+        "production": (f"{cfg.nx}x{cfg.ny}x{cfg.nz} production box of Table 2 (30x30x60, ellipsoidal anomaly, "
+                       "background shear 1, power law n=3, R0=2000, dtS rule), thesis PT schedule"),
+    }
     out = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -360,11 +382,7 @@ def main(argv=None):
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": (f"{n}^3 two-anomaly porosity grid, lognormal k0 (sigma 0.5), "
-                         "Drucker-Prager cap C=1 30deg, thesis PT schedule (refresh/norms every 15)")
-            if args.workload == "anomaly" else
-            (f"{n}^3 porosity-wave domain (L=30, three sources of width 1), scalar k0, "
-             "Drucker-Prager cap, dt 5e-4, thesis PT schedule (refresh/norms every 15)"),
+            "workload": workloads[args.workload],
             "n": n, "cells": cfg.ncell, "precision": "fp64", "schedule": "thesis",
             "step": f"one refresh cycle: refresh + {nup} PT iterations (norms on the last)",
             "parallelism": "single GPU",
@@ -390,6 +408,8 @@ def main(argv=None):
         "copy_gbs": round(copy_gbs, 1),
         "wall_s_timed": round(t_wall, 3),
         "norms_last_check": norms,
+        "decompaction_flips": flips,
+        "weakened_cell_fraction": round(weakened, 6),
         "kernel_source_sha": kernel_source_sha(),
     }
     g.close()

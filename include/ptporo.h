@@ -61,7 +61,7 @@
 extern "C" {
 #endif
 
-#define PT_ABI_VERSION 1
+#define PT_ABI_VERSION 2
 
 typedef struct pt_grid pt_grid;
 
@@ -105,6 +105,14 @@ typedef enum {
                                no cap; its plasticity is the power law of eq (24))  */
 #define PT_F_K0FIELD  4u   /* k0 is the per-cell field PT_K0, else the scalar kmuf0   */
 #define PT_F_MECHOFF  8u   /* freeze V and Pt (linear fluid-pressure diffusion limit) */
+#define PT_F_FP32_TALL 16u /* launch shape only: the FP32 correction sweep always takes its
+                              14-row tiles (else the launch cost model picks 10 or 14 rows);
+                              every tiling gives bitwise the same fields                  */
+#define PT_F_DTS_RULE 32u  /* stress-history step of the appendix two-phase script (per-step
+                              block): each pt_begin_step sets dtS = max(mu_s) / (G xi_w) and
+                              renews the history when the time accumulated since the last
+                              renewal (dt per step) reaches it; the first step of a run keeps
+                              the zero history.  The update_history arguments are ignored. */
 
 /* Non-dimensional physical and numerical parameters (article 1, Table 2 and
  * the appendix two-phase script; the readings of ambiguous values are listed
@@ -131,6 +139,12 @@ typedef struct {
     int32_t nup;                    /* iterations between refreshes / checks           */
     int32_t pad_;
     double r_eta, r_mu;             /* log-relaxation of the thesis schedule           */
+    double shear_bg;                /* background simple shear rate d(Vx_bg)/dy = tau_bg/mu0
+                                       (eq (32)); 0 = none.  It enters the xy strain rate on
+                                       every xy edge; on boundary xy edges, where the solved
+                                       (perturbation) velocity slips freely, it is the only
+                                       strain rate, with the viscosity of the cells inside  */
+    double xsi_w;                   /* wanted xi of the PT_F_DTS_RULE step (> 0 with it)   */
 } pt_params;
 
 /* Residual norms and one-iteration changes (all infinity norms).
@@ -277,7 +291,8 @@ pt_status pt_set_porosity(pt_grid* g, const void* phi_dev);
  * (pt_solve_linear); cur: the copy holding the present value of each
  * double-buffered field; mixed_copy, mixed_clean: the mixed workspace copy
  * that holds the FP32 damped residual and whether the workspace is
- * initialised (kept only if the mixed workspace is bound when set). */
+ * initialised (kept only if the mixed workspace is bound when set); steps,
+ * dt_cum, dts: the stress-history step rule's state (PT_F_DTS_RULE). */
 typedef struct {
     int32_t version;                /* PT_ABI_VERSION                                  */
     int32_t refreshed;
@@ -286,6 +301,8 @@ typedef struct {
     double ref_v, ref_p;
     int32_t cur[PT_NPING];
     int32_t mixed_clean;
+    int64_t steps;                  /* pt_begin_step calls since creation or reset     */
+    double dt_cum, dts;             /* PT_F_DTS_RULE: time since the last renewal; dtS */
 } pt_counters;
 pt_status pt_get_counters(const pt_grid* g, pt_counters* out);
 pt_status pt_set_counters(pt_grid* g, const pt_counters* in);

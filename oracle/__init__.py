@@ -71,7 +71,7 @@ class _Params(C.Structure):
                 ("powerlaw", C.c_int32), ("dpcap", C.c_int32), ("mech_off", C.c_int32),
                 ("k0field", C.c_int32), ("ngx", C.c_int32), ("ngy", C.c_int32), ("ngz", C.c_int32),
                 ("hx", C.c_double), ("hy", C.c_double), ("hz", C.c_double),
-                ("variant", C.c_int32)]
+                ("variant", C.c_int32), ("shear_bg", C.c_double)]
 
 
 _STATE_FIELDS = ("vx", "vy", "vz", "pt", "pf", "lp", "rx", "ry", "rz", "pto", "pfo",
@@ -106,6 +106,9 @@ def _load():
         lib.or_last_stresses.argtypes = [C.c_void_p] + [P(C.c_double)] * 6
         lib.or_last_fluxes.argtypes = [C.c_void_p] + [P(C.c_double)] * 3
         lib.or_num_threads.restype = C.c_int
+        lib.or_set_dts.argtypes = [C.c_void_p, C.c_double]
+        lib.or_max_mus.argtypes = [C.c_void_p, P(_State)]
+        lib.or_max_mus.restype = C.c_double
         lib.or_set_num_threads.argtypes = [C.c_int]
         lib.or_heat1d_step.restype = C.c_int
         lib.or_heat1d_step.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double,
@@ -151,7 +154,7 @@ class Oracle:
         self.lib = _load()
         p = _Params()
         p.nx, p.ny, p.nz = nx, ny, nz
-        for name, _ in _Params._fields_[3:-11]:
+        for name, _ in _Params._fields_[3:-12]:
             setattr(p, name, float(getattr(phys, name)))
         if global_counts is not None:
             # a window of a (gx, gy, gz) grid on the full domain of phys
@@ -163,6 +166,7 @@ class Oracle:
         p.mech_off = int(bool(phys.mech_off))
         p.k0field = int(k0 is not None)
         p.variant = int(variant)
+        p.shear_bg = float(getattr(phys, "shear_bg", 0.0))
         self._params = p
         self.ctx = self.lib.or_create(C.byref(p))
         if not self.ctx:
@@ -187,6 +191,10 @@ class Oracle:
         self._bind()
         self.refreshed = False
         self.step_index = 0
+        # stress-history step rule of the script (per-step block): the
+        # accumulated time since the last history update starts at dt
+        self.dt_cum = float(phys.dt)
+        self.dts = float(phys.dtS)
         self.iter = 0          # iteration counter within the current step
         self.total_iters = 0
         self.history = []      # norms at each check
@@ -218,13 +226,32 @@ class Oracle:
 
     # ---- primitives ---------------------------------------------------------
     def begin_step(self):
-        """Old values; stress history from the current state from step 2 on."""
-        self.lib.or_begin_step(self.ctx, C.byref(self._st), int(self.step_index >= 1))
+        """Old values; stress history from the current state from step 2 on.
+
+        With the stress-history step rule (phys.dts_rule, the script's
+        per-step block): dtS = max(mu_s) / (G xi_w) each step; the history is
+        renewed (with the stresses of the previous dtS) when the time
+        accumulated since the last renewal reaches the new dtS, and that
+        accumulation restarts; the first step keeps the zero history."""
+        ph = self.phys
+        if getattr(ph, "dts_rule", False):
+            dts_new = float(self.lib.or_max_mus(self.ctx, C.byref(self._st))) / (ph.G * ph.xsi_w)
+            renew = self.step_index >= 1 and self.dt_cum >= dts_new
+            self.lib.or_begin_step(self.ctx, C.byref(self._st), int(renew))
+            if renew or self.step_index == 0:
+                self.dt_cum = 0.0
+            self.dts = dts_new
+            self.lib.or_set_dts(self.ctx, dts_new)
+            self.history_renewed = renew
+        else:
+            self.lib.or_begin_step(self.ctx, C.byref(self._st), int(self.step_index >= 1))
+            self.history_renewed = self.step_index >= 1
         self.iter = 0
         self.ref = None        # residual reference of the step, set by its first solve
 
     def end_step(self):
         self.step_index += 1
+        self.dt_cum += float(self.phys.dt)
 
     def refresh(self, r_eta=None, r_mu=None):
         ph = self.phys

@@ -53,6 +53,12 @@ typedef struct {
      * the converged solution; tests use them to show why a reading was
      * taken. */
     int32_t variant;
+    /* Background simple shear (article 1, eq (32)): the shear rate
+     * d(Vx_bg)/dy of a background velocity Vx_bg(y) that enters the xy
+     * strain rate on every xy-edge (0: none).  The solved velocity is the
+     * perturbation; on boundary xy-edges its own strain rate is zero (free
+     * slip), so they carry the background part alone. */
+    double shear_bg;
 } or_params;
 
 /* beta_n r_Pt in the normal stresses evaluated at the updated Pt' instead of
@@ -332,6 +338,7 @@ static void stresses(or_ctx *c, const or_state *st, int with_betan)
                 c->tyy[q] = a * st->syy[q] + b * (eyy + comp);
                 c->tzz[q] = a * st->szz[q] + b * (ezz + comp);
             }
+    const double gbg = p->shear_bg;
 #pragma omp parallel for
     for (int k = 0; k < NZ; ++k)
         for (int j = 0; j <= NY; ++j)
@@ -345,7 +352,24 @@ static void stresses(or_ctx *c, const or_state *st, int with_betan)
                     double b = 2.0 * mue / (1.0 + xie);
                     double exy = 0.5 * ((st->vx[IFX(i, j, k)] - st->vx[IFX(i, j - 1, k)]) / c->dy
                                       + (st->vy[IFY(i, j, k)] - st->vy[IFY(i - 1, j, k)]) / c->dx);
+                    if (gbg != 0.0) exy += 0.5 * gbg;
                     t = a * st->sxy[IEXY(i, j, k)] + b * exy;
+                } else if (gbg != 0.0) {
+                    /* boundary edge: the background strain rate only, with
+                     * the viscosity averaged over the cells inside */
+                    double sum = 0.0;
+                    int cnt = 0;
+                    for (int jj = j - 1; jj <= j; ++jj)
+                        for (int ii = i - 1; ii <= i; ++ii)
+                            if (ii >= 0 && ii < NX && jj >= 0 && jj < NY) {
+                                sum += st->mus[IC(ii, jj, k)];
+                                ++cnt;
+                            }
+                    double mue = sum / cnt;
+                    double xie = mue / gdt;
+                    double a = xie / (1.0 + xie);
+                    double b = 2.0 * mue / (1.0 + xie);
+                    t = a * st->sxy[IEXY(i, j, k)] + b * (0.5 * gbg);
                 }
                 c->txy[IEXY(i, j, k)] = t;
             }
@@ -784,6 +808,20 @@ void or_tau_ii(or_ctx *c, const or_state *st, double *out)
                 out[q] = sqrt(0.5 * (c->txx[q] * c->txx[q] + c->tyy[q] * c->tyy[q] + c->tzz[q] * c->tzz[q])
                               + axy * axy + axz * axz + ayz * ayz);
             }
+}
+
+/* Stress-history time step (the script recomputes it every physical step). */
+void or_set_dts(or_ctx *c, double dts)
+{
+    c->p.dtS = dts;
+}
+
+/* Largest lagged shear viscosity mu_s over the cells. */
+double or_max_mus(const or_ctx *c, const or_state *st)
+{
+    double m = 0.0;
+    for (size_t q = 0; q < c->nc; ++q) m = nmax(m, st->mus[q]);
+    return m;
 }
 
 /* Copies of the last computed stresses and Darcy fluxes, for tests. */

@@ -7,7 +7,7 @@ import os
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libptporo.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 FIELDS = ("vx", "vy", "vz", "pt", "pf", "lp", "rx", "ry", "rz", "pto", "pfo", "lpo",
           "sxx", "syy", "szz", "sxy", "sxz", "syz", "fox", "foy", "foz", "mn", "k0",
@@ -15,7 +15,7 @@ FIELDS = ("vx", "vy", "vz", "pt", "pf", "lp", "rx", "ry", "rz", "pto", "pfo", "l
 FIELD_ID = {n: i for i, n in enumerate(FIELDS)}
 NPING = 9
 
-F_POWERLAW, F_DPCAP, F_K0FIELD, F_MECHOFF = 1, 2, 4, 8
+F_POWERLAW, F_DPCAP, F_K0FIELD, F_MECHOFF, F_FP32_TALL, F_DTS_RULE = 1, 2, 4, 8, 16, 32
 ADJ_CHECKPOINT, ADJ_MIXED = 1, 2
 
 STATUS = {0: "PT_OK", 1: "PT_ENOTCONV", -1: "PT_EINVAL", -2: "PT_EDEVICE",
@@ -35,7 +35,8 @@ class Params(C.Structure):
                 ("dt", C.c_double), ("dtS", C.c_double), ("beta_n", C.c_double),
                 ("rho_i", C.c_double), ("c_v", C.c_double), ("c_pf", C.c_double),
                 ("damp_c", C.c_double), ("nup", C.c_int32), ("pad_", C.c_int32),
-                ("r_eta", C.c_double), ("r_mu", C.c_double)]
+                ("r_eta", C.c_double), ("r_mu", C.c_double),
+                ("shear_bg", C.c_double), ("xsi_w", C.c_double)]
 
 
 class Norms(C.Structure):
@@ -46,7 +47,8 @@ class Counters(C.Structure):
     _fields_ = [("version", C.c_int32), ("refreshed", C.c_int32), ("iter", C.c_int64),
                 ("ref_set", C.c_int32), ("mixed_copy", C.c_int32),
                 ("ref_v", C.c_double), ("ref_p", C.c_double),
-                ("cur", C.c_int32 * NPING), ("mixed_clean", C.c_int32)]
+                ("cur", C.c_int32 * NPING), ("mixed_clean", C.c_int32),
+                ("steps", C.c_int64), ("dt_cum", C.c_double), ("dts", C.c_double)]
 
 
 EXPORTS = ["pt_create", "pt_destroy", "pt_field_elems", "pt_bind_field", "pt_workspace_size",
@@ -154,6 +156,10 @@ def params_from(phys, k0field: bool) -> Params:
         flags |= F_K0FIELD
     if phys.mech_off:
         flags |= F_MECHOFF
+    if getattr(phys, "fp32_tall", False):
+        flags |= F_FP32_TALL
+    if getattr(phys, "dts_rule", False):
+        flags |= F_DTS_RULE
     p.flags = flags
     for name, ctype in Params._fields_:
         if ctype is C.c_double:

@@ -35,6 +35,9 @@ struct pt_grid {
     bool norms_pending = false;
     bool broken = false;       // PT_ESTATE: a divergence, domain or device error occurred
     double* nw = nullptr;      // norm area in place of the workspace (pt_solve_linear_static)
+    int64_t steps = 0;         // pt_begin_step calls since creation or reset
+    double dt_cum = 0.0;       // PT_F_DTS_RULE: time accumulated since the last history renewal
+    double dts = 0.0;          // PT_F_DTS_RULE: the present stress-history step
     pt_progress_fn progress = nullptr;   // per-stage report of long calls
     void* progress_user = nullptr;
     std::string err;
@@ -68,6 +71,8 @@ bool valid_params(const pt_params* p) {
     for (double v : pos)
         if (!(v > 0.0) || !std::isfinite(v)) return false;
     if (!(p->phi0 < 1.0) || p->nup < 1 || p->beta_d < 0.0 || p->beta_phi < 0.0 || p->beta_n < 0.0) return false;
+    if (!std::isfinite(p->shear_bg)) return false;
+    if ((p->flags & PT_F_DTS_RULE) && !(p->xsi_w > 0.0 && std::isfinite(p->xsi_w))) return false;
     return true;
 }
 
@@ -90,7 +95,10 @@ void make_coef(pt_grid* g) {
     c.rhosg = p.rhosg;
     c.rhobg = p.rhofg * p.phi0 + (1.0 - p.phi0) * p.rhosg;
     c.buoy = p.rhofg - c.rhobg;
-    c.gdts_inv = 1.0 / (p.G * p.dtS);
+    // the stress-history step: the parameter, or the rule's present value
+    const double dts = ((p.flags & PT_F_DTS_RULE) && g->dts > 0.0) ? g->dts : p.dtS;
+    c.gdts_inv = 1.0 / (p.G * dts);
+    c.gbg_half = 0.5 * p.shear_bg;
     c.beta_n = p.beta_n;
     c.rho_i_inv = 1.0 / p.rho_i;
     c.dtauv_c = p.rho_i * h * h / (p.c_v * (1.0 + p.beta_n));
@@ -102,6 +110,7 @@ void make_coef(pt_grid* g) {
     c.ab = p.alpha / p.B;
     c.third = 1.0 / 3.0;
     c.mech_off = (p.flags & PT_F_MECHOFF) ? 1 : 0;
+    g->geom.tall32 = (p.flags & PT_F_FP32_TALL) ? 1 : 0;
 }
 
 RefreshCoef make_refresh(const pt_grid* g, double r_eta, double r_mu) {
@@ -294,6 +303,24 @@ pt_status read_norms(pt_grid* g, pt_norms* out) {
     return PT_OK;
 }
 
+// Largest value of a cell field (synchronises; uses the norm area, so the
+// last norms are no longer readable).
+pt_status cells_max(pt_grid* g, const double* f, double* out) {
+    const int64_t nb = norm_blocks(g->geom);
+    double* area = norm_area(g);
+    hipError_t e = launch_cell_max(g->geom, f, area, nb, g->stream);
+    if (e == hipSuccess) e = launch_reduce_max(area, nb, area + nb * NNORM, g->stream);
+    double host = 0.0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&host, area + nb * NNORM, sizeof(double), hipMemcpyDeviceToHost, g->stream);
+    const hipError_t es = hipStreamSynchronize(g->stream);
+    if (e == hipSuccess) e = es;
+    if (e != hipSuccess) return hip_fail(g, e, "cell maximum");
+    g->norms_pending = false;
+    if (!std::isfinite(host)) return fail(g, PT_EDIVERGED, "non-finite viscosity");
+    *out = host;
+    return PT_OK;
+}
+
 // The domain flag alone (synchronises).
 pt_status read_domain(pt_grid* g) {
     double flag = 0.0;
@@ -341,6 +368,8 @@ pt_status pt_create(int32_t nx, int32_t ny, int32_t nz, int64_t row_pitch, const
     g->geom.S = row_pitch * (int64_t)(ny + 1);
     g->geom.kz = KZ_MAX;   // each sweep variant sets its own chunk at launch
     g->prm = *params;
+    g->dt_cum = params->dt;
+    g->dts = params->dtS;
     std::memset(g->f, 0, sizeof(g->f));
     std::memset(g->cur, 0, sizeof(g->cur));
     // compute units of the current device for the launch cost model (the
@@ -425,14 +454,34 @@ pt_status pt_begin_step(pt_grid* g, int32_t update_history) {
     // that a mixed step depends only on the state it starts from
     g->mws_clean = false;
     g->mx_copy = 0;
+    const bool rule = (g->prm.flags & PT_F_DTS_RULE) != 0;
+    double dts_new = 0.0;
+    if (rule) {
+        // the script's per-step block: dtS = max(mu_s) / (G xi_w); the history
+        // is renewed (with the stresses of the previous dtS) when the time
+        // accumulated since the last renewal reaches it
+        if (g->steps >= 1) g->dt_cum += g->prm.dt;
+        double mx = 0.0;
+        st = cells_max(g, cur(g, PT_MUS), &mx);
+        if (st != PT_OK) return st;
+        dts_new = mx / (g->prm.G * g->prm.xsi_w);
+        update_history = (g->steps >= 1 && g->dt_cum >= dts_new) ? 1 : 0;
+    }
     const AuxPtrs a = aux(g);
     hipError_t e = launch_begin_step(g->geom, g->coef, a, update_history, g->stream);
     if (e != hipSuccess) return hip_fail(g, e, "begin_step");
-    if (update_history) {
+    if (rule) {
+        if (update_history || g->steps == 0) g->dt_cum = 0.0;
+        g->dts = dts_new;
+        make_coef(g);
+    }
+    if (update_history || rule) {
+        // the folded history term with this step's Maxwell coefficients
         const RefreshCoef r = make_refresh(g, 1.0, 1.0);
         e = launch_fo(g->geom, g->coef, r, a, g->stream);
         if (e != hipSuccess) return hip_fail(g, e, "fo");
     }
+    g->steps += 1;
     g->iter = 0;
     g->ref_set = false;
     return PT_OK;
@@ -644,6 +693,10 @@ pt_status pt_reset_state(pt_grid* g) {
     }
     std::memset(g->cur, 0, sizeof(g->cur));
     g->iter = 0;
+    g->steps = 0;
+    g->dt_cum = g->prm.dt;
+    g->dts = g->prm.dtS;
+    make_coef(g);
     g->ref_set = false;
     g->refreshed = false;
     g->norms_pending = false;
@@ -664,13 +717,17 @@ pt_status pt_get_counters(const pt_grid* g, pt_counters* out) {
     for (int f = 0; f < PT_NPING; ++f) out->cur[f] = g->cur[f];
     out->mixed_copy = g->mx_copy;
     out->mixed_clean = g->mws_clean ? 1 : 0;
+    out->steps = g->steps;
+    out->dt_cum = g->dt_cum;
+    out->dts = g->dts;
     return PT_OK;
 }
 
 pt_status pt_set_counters(pt_grid* g, const pt_counters* in) {
     if (!g || !in) return PT_EINVAL;
     if (in->version != PT_ABI_VERSION || in->iter < 0 || (in->mixed_copy & ~1) || (in->mixed_clean & ~1) ||
-        (in->refreshed & ~1) || (in->ref_set & ~1))
+        (in->refreshed & ~1) || (in->ref_set & ~1) || in->steps < 0 || !std::isfinite(in->dt_cum) ||
+        !(in->dts > 0.0 && std::isfinite(in->dts)))
         return fail(g, PT_EINVAL, "bad counters");
     for (int f = 0; f < PT_NPING; ++f)
         if (in->cur[f] & ~1) return fail(g, PT_EINVAL, "bad copy index in counters");
@@ -683,6 +740,10 @@ pt_status pt_set_counters(pt_grid* g, const pt_counters* in) {
     // the mixed workspace's contents count as kept only if it is bound
     g->mx_copy = in->mixed_copy;
     g->mws_clean = g->mws && in->mixed_clean != 0;
+    g->steps = in->steps;
+    g->dt_cum = in->dt_cum;
+    g->dts = in->dts;
+    make_coef(g);
     return PT_OK;
 }
 
@@ -1062,6 +1123,7 @@ pt_status mixed_transposed_solve(pt_grid* g, const double* lp, const double* kc,
     t.coef.rhosg = 0.0;
     t.coef.rhobg = 0.0;
     t.coef.buoy = 0.0;
+    t.coef.gbg_half = 0.0;
     double rv = 0.0, rp = 0.0, rho = 0.0;
     bool ref_set = false;
     int copy = 0;
@@ -1262,6 +1324,8 @@ pt_status pt_adjoint_run(pt_grid* g, int32_t n_steps, int32_t n_picard, int32_t 
     if (st != PT_OK) return st;
     if (g->prm.flags & (PT_F_POWERLAW | PT_F_DPCAP | PT_F_MECHOFF))
         return fail(g, PT_EINVAL, "the run adjoint needs the Newtonian viscosity law with mechanics on");
+    if (g->prm.shear_bg != 0.0 || (g->prm.flags & PT_F_DTS_RULE))
+        return fail(g, PT_EINVAL, "the run adjoint does not cover the background shear or the dtS rule");
     if (!(g->prm.flags & PT_F_K0FIELD)) return fail(g, PT_EINVAL, "the run adjoint needs a k0 field");
     if (options & ~(PT_ADJ_CHECKPOINT | PT_ADJ_MIXED)) return fail(g, PT_EINVAL, "unknown run-adjoint option");
     const bool checkpoint = (options & PT_ADJ_CHECKPOINT) != 0;

@@ -68,10 +68,21 @@ struct StressEval {
         tzz = aa * a.szz[o] + bb * (dzv - d3);
     }
     __device__ double xy(int i, int j, int k) const {
-        if (i < 1 || i >= g.nx || j < 1 || j >= g.ny) return 0.0;
+        if (i < 1 || i >= g.nx || j < 1 || j >= g.ny) {
+            if (c.gbg_half == 0.0) return 0.0;
+            // boundary edge under the background shear of eq (32): the
+            // background strain rate alone, viscosity of the cells inside
+            double sum = 0.0;
+            for (int jj = j - 1; jj <= j; ++jj)
+                for (int ii = i - 1; ii <= i; ++ii)
+                    if (ii >= 0 && ii < g.nx && jj >= 0 && jj < g.ny) sum += mus(ii, jj, k);
+            const double mue = sum / (double)(((i >= 1) + (i < g.nx)) * ((j >= 1) + (j < g.ny)));
+            return coef_a(mue, c.gdts_inv) * a.sxy[at(g, i, j, k)] + coef_b(mue, c.gdts_inv) * c.gbg_half;
+        }
         const double mue = 0.25 * (mus(i - 1, j - 1, k) + mus(i, j - 1, k) + mus(i - 1, j, k) + mus(i, j, k));
         const int64_t o = at(g, i, j, k);
-        const double e = 0.5 * ((a.vx[o] - a.vx[at(g, i, j - 1, k)]) * c.dyi + (a.vy[o] - a.vy[at(g, i - 1, j, k)]) * c.dxi);
+        const double e = 0.5 * ((a.vx[o] - a.vx[at(g, i, j - 1, k)]) * c.dyi + (a.vy[o] - a.vy[at(g, i - 1, j, k)]) * c.dxi) +
+                         c.gbg_half;
         return coef_a(mue, c.gdts_inv) * a.sxy[o] + coef_b(mue, c.gdts_inv) * e;
     }
     __device__ double xz(int i, int j, int k) const {
@@ -187,6 +198,33 @@ __global__ __launch_bounds__(AB) void k_set_porosity(Geom g, const double* __res
     const double l = log(1.0 - p);
     lp[o] = l;
     lpo[o] = l;
+}
+
+// Per-block maxima of a cell field over its cell extent (grid-stride over
+// the cells); partials[b * 8] gets the block's maximum, the other slots 0.
+__global__ __launch_bounds__(AB) void k_cell_max(Geom g, const double* __restrict__ f, double* __restrict__ partials) {
+    __shared__ double red[AB / 64];
+    const int64_t ncell = (int64_t)g.nx * g.ny * g.nz;
+    double m = -1.0e300;
+    for (int64_t t = (int64_t)blockIdx.x * AB + threadIdx.x; t < ncell; t += (int64_t)gridDim.x * AB) {
+        const int i = (int)(t % g.nx), j = (int)((t / g.nx) % g.ny), k = (int)(t / ((int64_t)g.nx * g.ny));
+        const double v = f[at(g, i, j, k)];
+        m = (v > m || v != v) ? v : m;
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+        const double v = __shfl_xor(m, off, 64);
+        m = (v > m || v != v) ? v : m;
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x < NNORM) {
+        double r = 0.0;
+        if (threadIdx.x == 0) {
+            r = red[0];
+            for (int w = 1; w < AB / 64; ++w) r = (red[w] > r || red[w] != red[w]) ? red[w] : r;
+        }
+        partials[(int64_t)blockIdx.x * NNORM + threadIdx.x] = r;
+    }
 }
 
 __global__ __launch_bounds__(AB) void k_fill(double* __restrict__ dst, double v, int64_t n) {
@@ -336,6 +374,11 @@ hipError_t launch_porosity_step(const Geom& g, const Coef& c, const AuxPtrs& a, 
 hipError_t launch_set_porosity(const Geom& g, const double* phi, double* lp, double* lpo, double* domain,
                                hipStream_t s) {
     hipLaunchKernelGGL(k_set_porosity, box_grid(g), dim3(AB), 0, s, g, phi, lp, lpo, domain);
+    return hipGetLastError();
+}
+
+hipError_t launch_cell_max(const Geom& g, const double* f, double* partials, int64_t nblocks, hipStream_t s) {
+    if (nblocks > 0) hipLaunchKernelGGL(k_cell_max, dim3((unsigned)nblocks), dim3(AB), 0, s, g, f, partials);
     return hipGetLastError();
 }
 

@@ -69,7 +69,7 @@ __device__ __forceinline__ T nanmax(T m, T v) {
 template <typename T>
 struct CT {
     T dxi, dyi, dzi, dt, dti, beta_d, alpha, beta_phi, rhofg, rhosg, rhobg, buoy, gdts_inv, beta_n,
-        rho_i_inv, dtauv_c, dtaupt_c, dtaupf_c, dampx, dampy, dampz, ab, third;
+        rho_i_inv, dtauv_c, dtaupt_c, dtaupf_c, dampx, dampy, dampz, ab, third, gbg_half;
     int mech_off;
     __device__ explicit CT(const Coef& c)
         : dxi(T(c.dxi)), dyi(T(c.dyi)), dzi(T(c.dzi)), dt(T(c.dt)), dti(T(c.dti)), beta_d(T(c.beta_d)),
@@ -77,11 +77,13 @@ struct CT {
           rhobg(T(c.rhobg)), buoy(T(c.buoy)), gdts_inv(T(c.gdts_inv)), beta_n(T(c.beta_n)),
           rho_i_inv(T(c.rho_i_inv)), dtauv_c(T(c.dtauv_c)), dtaupt_c(T(c.dtaupt_c)),
           dtaupf_c(T(c.dtaupf_c)), dampx(T(c.dampx)), dampy(T(c.dampy)), dampz(T(c.dampz)),
-          ab(T(c.ab)), third(T(c.third)), mech_off(c.mech_off) {}
+          ab(T(c.ab)), third(T(c.third)), gbg_half(T(c.gbg_half)), mech_off(c.mech_off) {}
 };
 
-// HV, if not 0, overrides the variant's block height.
-template <typename T, int MODE, bool NORMS, int HV = 0>
+// HV, if not 0, overrides the variant's block height.  BGS: the background
+// shear of eq (32) is on (a variant of its own: the plain thesis sweep has no
+// register to spare for it).
+template <typename T, int MODE, bool NORMS, int HV = 0, bool BGS = false>
 __global__ __launch_bounds__((sweep_bx<T, MODE, NORMS>() * (HV ? HV : sweep_by<T, MODE, NORMS>()))) void k_sweep(
     Geom g, Coef cd, SweepPtrs<T> p) {
     constexpr int W = sweep_bx<T, MODE, NORMS>();
@@ -322,8 +324,18 @@ __global__ __launch_bounds__((sweep_bx<T, MODE, NORMS>() * (HV ? HV : sweep_by<T
                 const T mue = quarter * (sh.mu[ty - 1][tx - 1] + sh.mu[ty - 1][tx] + sh.mu[ty][tx - 1] + mu_c);
                 const T xie = mue * c.gdts_inv;
                 const T be = two * mue / (one + xie);
-                const T exy = half * ((vx_c - sh.vx[ty - 1][tx]) * c.dyi + (vy_c - sh.vy[ty][tx - 1]) * c.dxi);
+                T exy = half * ((vx_c - sh.vx[ty - 1][tx]) * c.dyi + (vy_c - sh.vy[ty][tx - 1]) * c.dxi);
+                if constexpr (BGS) exy += c.gbg_half;   // background shear (eq (32))
                 txy = be * exy;
+            } else if (BGS && plc && i >= 0 && i <= g.nx && j >= 0 && j <= g.ny) {
+                // boundary edge: the perturbation slips freely, the background
+                // strain rate remains; viscosity averaged over the cells inside
+                // (the staged values outside the domain are zero)
+                const T cnt = T(((i >= 1) + (i < g.nx)) * ((j >= 1) + (j < g.ny)));
+                const T mue = (sh.mu[ty - 1][tx - 1] + sh.mu[ty - 1][tx] + sh.mu[ty][tx - 1] + mu_c) / cnt;
+                const T xie = mue * c.gdts_inv;
+                const T be = two * mue / (one + xie);
+                txy = be * c.gbg_half;
             }
             const bool lev = (pz + 1 >= 1) && (pz + 1 < g.nz);
             if (lev && i >= 1 && i < g.nx && cj) {
@@ -519,8 +531,13 @@ template <typename T, int MODE, bool NORMS, int HV = 0>
 void launch_sweep(const Geom& g, const Coef& c, const SweepPtrs<T>& p, hipStream_t s) {
     constexpr int W = sweep_bx<T, MODE, NORMS>(), H = HV ? HV : sweep_by<T, MODE, NORMS>();
     const Geom v = sweep_geom(g, W, H);
-    hipLaunchKernelGGL((k_sweep<T, MODE, NORMS, HV>), dim3((unsigned)iter_grid_blocks(g, W, H)), dim3(W * H, 1, 1), 0,
-                       s, v, c, p);
+    // the correction system has no background term (it is in its right-hand side)
+    if (MODE != MD_CORR && c.gbg_half != 0.0)
+        hipLaunchKernelGGL((k_sweep<T, MODE, NORMS, HV, MODE != MD_CORR>), dim3((unsigned)iter_grid_blocks(g, W, H)),
+                           dim3(W * H, 1, 1), 0, s, v, c, p);
+    else
+        hipLaunchKernelGGL((k_sweep<T, MODE, NORMS, HV, false>), dim3((unsigned)iter_grid_blocks(g, W, H)),
+                           dim3(W * H, 1, 1), 0, s, v, c, p);
 }
 
 hipError_t launch_iteration(const Geom& g, const Coef& c, const SweepPtrs<double>& p, int mode, int norms,

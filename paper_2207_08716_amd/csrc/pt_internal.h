@@ -20,6 +20,7 @@ struct Geom {
     int64_t S;   // plane pitch = (ny + 1) * P
     int kz;      // planes per z chunk of a sweep (set per sweep variant at launch)
     int cus = DEFAULT_CUS;   // compute units of the device (one sweep block each)
+    int tall32 = 0;          // FP32 correction sweep: always the 14-row tiles
 };
 
 // Physical and numerical constants, in the form the kernels use them.
@@ -39,6 +40,7 @@ struct Coef {
     double dampx, dampy, dampz;    // 1 - damp_c / n
     double ab;                     // alpha / B
     double third;                  // 1/3
+    double gbg_half;               // half the background shear rate (xy strain rate of eq (32)), 0: none
     int mech_off;
 };
 
@@ -124,6 +126,7 @@ inline int64_t tiling_cost(const Geom& g, int bx, int by) {
 // (measured: 10 rows 19 % faster at 127^3 and 7 % at 255^3, 14 rows 12 %
 // faster at 511^3; the cost model picks the same in all three).
 inline bool corr32_short(const Geom& g) {
+    if (g.tall32) return false;
     return tiling_cost(g, BX, BY_CORR32_SHORT) < tiling_cost(g, BX, BY_CORR32);
 }
 
@@ -267,5 +270,8 @@ hipError_t launch_adj_oldvalues(const Geom& g, const Coef& c, const double* rpt,
                                 double* pfo, hipStream_t s);
 hipError_t launch_absmax5(const Geom& g, const double* const* f, double* partials, int64_t nblocks,
                           hipStream_t s);
+// Per-block maxima of a cell field (its cell extent only) into partials[b * 8]
+// (the other seven slots 0), nblocks blocks.
+hipError_t launch_cell_max(const Geom& g, const double* f, double* partials, int64_t nblocks, hipStream_t s);
 
 }  // namespace ptk

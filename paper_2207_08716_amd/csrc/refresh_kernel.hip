@@ -60,8 +60,10 @@ __global__ __launch_bounds__(RW * RH) void k_refresh_tiled(Geom g, Coef c, Refre
 
     const bool edge = tx >= 1 && ty >= 1;   // LDS neighbours at tx-1, ty-1 exist
     const bool outc = tx >= 1 && tx <= W - 2 && ty >= 1 && ty <= H - 2 && i < g.nx && j < g.ny;
-    // edges computed by this thread (interior edges only; boundary edges are zero)
+    // edges computed by this thread (interior edges; boundary edges are zero
+    // except for xy edges under the background shear of eq (32))
     const bool exy = edge && i >= 1 && i < g.nx && j >= 1 && j < g.ny;
+    const bool bxy = edge && c.gbg_half != 0.0 && !exy && i >= 0 && i <= g.nx && j >= 0 && j <= g.ny;
     const bool exz = edge && i >= 1 && i < g.nx && j >= 0 && j < g.ny;
     const bool eyz = edge && j >= 1 && j < g.ny && i >= 0 && i < g.nx;
 
@@ -115,8 +117,24 @@ __global__ __launch_bounds__(RW * RH) void k_refresh_tiled(Geom g, Coef c, Refre
         const int lv = pz + 1;
         if (live && exy) {
             const double mue = 0.25 * (sh.mu0[ty - 1][tx - 1] + sh.mu0[ty - 1][tx] + sh.mu0[ty][tx - 1] + qc.mu);
-            const double e = 0.5 * ((qc.vx - sh.vx[ty - 1][tx]) * c.dyi + (qc.vy - sh.vy[ty][tx - 1]) * c.dxi);
+            const double e = 0.5 * ((qc.vx - sh.vx[ty - 1][tx]) * c.dyi + (qc.vy - sh.vy[ty][tx - 1]) * c.dxi) +
+                             c.gbg_half;
             txy = maxwell_a(mue, c.gdts_inv) * cc.sxy + maxwell_b(mue, c.gdts_inv) * e;
+        } else if (live && bxy) {
+            // boundary edge: background strain rate only, viscosity averaged
+            // over the cells inside
+            double sum = 0.0;
+            if (j >= 1) {
+                if (i >= 1) sum += sh.mu0[ty - 1][tx - 1];
+                if (i < g.nx) sum += sh.mu0[ty - 1][tx];
+            }
+            if (j < g.ny) {
+                if (i >= 1) sum += sh.mu0[ty][tx - 1];
+                if (i < g.nx) sum += qc.mu;
+            }
+            const double cnt = (double)(((i >= 1) + (i < g.nx)) * ((j >= 1) + (j < g.ny)));
+            const double mue = sum / cnt;
+            txy = maxwell_a(mue, c.gdts_inv) * cc.sxy + maxwell_b(mue, c.gdts_inv) * c.gbg_half;
         }
         if (exz && lv >= 1 && lv < g.nz) {
             const double mue = 0.25 * (sh.mu0[ty][tx - 1] + qc.mu + sh.mu1[ty][tx - 1] + qn.mu);
@@ -229,6 +247,8 @@ __global__ __launch_bounds__(RW * FH) void k_fo_tiled(Geom g, Coef c, RefreshCoe
     const bool exy = edge && i >= 1 && i < g.nx && j >= 1 && j < g.ny;
     const bool exz = edge && i >= 1 && i < g.nx && j >= 0 && j < g.ny;
     const bool eyz = edge && j >= 1 && j < g.ny && i >= 0 && i < g.nx;
+    // boundary xy edges carry a history under the background shear of eq (32)
+    const bool bxy = edge && c.gbg_half != 0.0 && !exy && i >= 0 && i <= g.nx && j >= 0 && j <= g.ny;
     // boundary faces at i = nx and j = ny belong to no cell: the halo thread
     // on them (in exactly one block) writes their zero
     const bool xbnd = trow && i == g.nx && j < g.ny;
@@ -278,6 +298,18 @@ __global__ __launch_bounds__(RW * FH) void k_fo_tiled(Geom g, Coef c, RefreshCoe
         double e_xy = 0.0, e_xz = 0.0, e_yz = 0.0;
         if (live && exy) {
             const double mue = 0.25 * (sh.mu0[ty - 1][tx - 1] + sh.mu0[ty - 1][tx] + sh.mu0[ty][tx - 1] + mu_c);
+            e_xy = maxwell_a(mue, c.gdts_inv) * cc.sxy;
+        } else if (live && bxy) {
+            double sum = 0.0;   // viscosity averaged over the cells inside
+            if (j >= 1) {
+                if (i >= 1) sum += sh.mu0[ty - 1][tx - 1];
+                if (i < g.nx) sum += sh.mu0[ty - 1][tx];
+            }
+            if (j < g.ny) {
+                if (i >= 1) sum += sh.mu0[ty][tx - 1];
+                if (i < g.nx) sum += mu_c;
+            }
+            const double mue = sum / (double)(((i >= 1) + (i < g.nx)) * ((j >= 1) + (j < g.ny)));
             e_xy = maxwell_a(mue, c.gdts_inv) * cc.sxy;
         }
         if (exz && lv >= 1 && lv < g.nz) {

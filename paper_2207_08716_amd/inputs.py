@@ -66,6 +66,10 @@ class Physics:
     powerlaw: bool = False    # eq (24) power-law shear viscosity
     dpcap: bool = False       # Drucker-Prager cap on the lagged viscosity
     mech_off: bool = False    # freeze V and Pt (linear Pf-diffusion limit)
+    fp32_tall: bool = False   # launch shape only: FP32 correction sweep on its 14-row tiles
+    shear_bg: float = 0.0     # background simple shear rate d(Vx_bg)/dy (eq (32)); 0: none
+    dts_rule: bool = False    # stress-history step dtS = max(mu_s)/(G xi_w), renewed when due
+    xsi_w: float = 1.0        # wanted xi of the dtS rule
 
     def replace(self, **kw) -> "Physics":
         return dataclasses.replace(self, **kw)
@@ -75,7 +79,7 @@ class Physics:
 class Anomaly:
     centre: tuple          # (x, y, z) in physical units
     amp: float             # amplitude in units of phi0
-    width: float           # Gaussian width w: exp(-|x-c|^2 / w^2)
+    width: float | tuple   # Gaussian width w: exp(-|x-c|^2 / w^2), or (wx, wy, wz) for an ellipsoid
 
 
 @dataclass
@@ -127,8 +131,13 @@ def porosity_field(cfg: Config) -> np.ndarray:
     phi = np.full(cfg.shape, p.phi0, dtype=np.float64)
     for a in cfg.anomalies:
         cx, cy, cz = a.centre
-        r2 = (x - cx) ** 2 + (y - cy) ** 2 + (z - cz) ** 2
-        phi += a.amp * p.phi0 * np.exp(-r2 / (a.width * a.width))
+        if isinstance(a.width, tuple):
+            wx, wy, wz = a.width
+            q = ((x - cx) / wx) ** 2 + ((y - cy) / wy) ** 2 + ((z - cz) / wz) ** 2
+            phi += a.amp * p.phi0 * np.exp(-q)
+        else:
+            r2 = (x - cx) ** 2 + (y - cy) ** 2 + (z - cz) ** 2
+            phi += a.amp * p.phi0 * np.exp(-r2 / (a.width * a.width))
     if cfg.noise_seed is not None:
         rng = np.random.Generator(np.random.PCG64(cfg.noise_seed))
         u = rng.random(cfg.shape)
@@ -253,12 +262,31 @@ def config_waves(n: int = 767, seed: int = 8) -> Config:
                   noise_seed=None, mode="picard", n_picard=5, rtol=1e-8, n_steps=20)
 
 
+def config_production(nx: int = 511, ny: int = 511, nz: int = 1022) -> Config:
+    """Production set-up of article 1, section 3.1 and Table 2: a 30 x 30 x 60
+    box under background simple shear (tau_bg / mu0 = 1, eq (32)) with an
+    ellipsoidal porosity anomaly of axes 14 x 14 x 3.5 (a Gaussian with
+    semi-axis widths 7, 7, 1.75, peak 2 phi0) at one fifth of the depth,
+    power-law shear viscosity (n = 3, tau0 = 0.04), decompaction factor
+    2000, K_phi = 333.33 (beta_phi = 1/K_phi, beta_d = 1.3 beta_phi),
+    G = 166.66, the stress-history step rule (xi_w = 1) and dt = 5e-6 (the
+    production run's 4800 steps to t = 2.4e-2)."""
+    beta_phi = 1.0 / 333.33
+    ph = Physics(lx=30.0, ly=30.0, lz=60.0, R0=2000.0, powerlaw=True, n_pow=3.0, tau0=0.04,
+                 beta_phi=beta_phi, beta_d=1.3 * beta_phi, G=166.66, shear_bg=1.0, dts_rule=True,
+                 xsi_w=1.0, dt=5e-6, dtS=5e-6)
+    return Config(name=f"production{nx}x{ny}x{nz}", nx=nx, ny=ny, nz=nz, phys=ph,
+                  anomalies=[Anomaly((15.0, 15.0, 12.0), 1.0, (7.0, 7.0, 1.75))],
+                  noise_seed=None, mode="thesis", n_iter=1000)
+
+
 CONFIGS = {
     "parity": config_parity,
     "picard": config_fp64_picard,
     "mixed": config_mixed,
     "adjoint": config_adjoint,
     "waves": config_waves,
+    "production": config_production,
 }
 
 
@@ -272,6 +300,6 @@ def initial_fields(cfg: Config) -> dict:
 
 
 __all__ = ["Physics", "Anomaly", "Config", "CONFIGS", "config_parity",
-           "config_fp64_picard", "config_mixed", "config_adjoint", "config_waves",
+           "config_fp64_picard", "config_mixed", "config_adjoint", "config_waves", "config_production",
            "initial_fields", "porosity_field", "k0_field", "gaussian_random_field",
            "sensor_cells", "random_centres", "cell_centres", "PICARD_DT"]

@@ -86,3 +86,43 @@ def test_mixed_picard_step_matches_fp64_127():
     worst = {k: _rel(out["mixed"][k], out["fp64"][k]) for k in out["fp64"]}
     print(worst, flush=True)
     assert max(worst.values()) <= 1e-5, worst
+
+
+def _flips_and_yield(g, ph):
+    """Cells at the decompaction switch (|Pf - Pt| below 1e-12 of the largest
+    pressure) and the fraction of cells whose viscosity the cap cut."""
+    pt, pf, mn = g.get("pt"), g.get("pf"), g.get("mn")
+    scale = max(np.abs(pt).max(), np.abs(pf).max(), 1e-300)
+    flips = int((np.abs(pf - pt) < 1e-12 * scale).sum())
+    return flips, float((mn < ph.mu0 * (1 - 1e-12)).mean())
+
+
+def test_mixed_workload_with_an_engaging_cap_matches_oracle():
+    """The mixed workload's recipe with a cohesion small enough for the cap to
+    engage (C = 4e-3, floor 2e-3: about 12 % of the cells yield; with C = 1
+    the stresses stay far below the yield stress, and below C ~ 1e-3 the
+    viscosity contrast makes the PT iteration diverge): a converged FP64
+    Picard step (5 stages to 1e-9) and the mixed one against the oracle's."""
+    n, rtol = 24, 1e-9
+    cfg = inputs.config_mixed(n)
+    cfg.phys = cfg.phys.replace(coh=4e-3, tau_y_min=2e-3)
+    g, o = _pair(cfg)
+    sweeps, rho, ok = g.picard_step(False, 5, rtol)
+    assert ok
+    counts = o.picard_step(5, rtol, 2_000_000)
+    flips, yielded = _flips_and_yield(g, cfg.phys)
+    print(f"GPU {sweeps} sweeps; oracle {[c[0] for c in counts]}; flips {flips}, yielded {yielded:.3f}",
+          flush=True)
+    assert yielded > 0.05
+    assert sweeps == sum(c[0] for c in counts)
+    worst = {k: _rel(g.get(k), o.f[k]) for k in ("vx", "vy", "vz", "pt", "pf", "lp", "mn")}
+    print(worst, flush=True)
+    assert max(worst.values()) <= 1e-7, worst
+    from paper_2207_08716_amd import schedules
+    f = inputs.initial_fields(cfg)
+    m = schedules.make_grid(cfg, f)
+    _s, _r, okm = m.picard_step(False, 5, rtol, mixed=True)
+    assert okm
+    worst = {k: _rel(m.get(k), o.f[k]) for k in ("vx", "vy", "vz", "pt", "pf", "lp")}
+    print("mixed", worst, flush=True)
+    assert max(worst.values()) <= 1e-5, worst

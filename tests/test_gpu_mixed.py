@@ -130,3 +130,38 @@ def test_mixed_stage_on_tall_fp32_tiles():
     worst = {name: _rel(gmx.get(name), g64.get(name)) for name in FIELDS}
     print(worst, flush=True)
     assert max(worst.values()) <= 1e-5, worst
+
+
+def test_forced_tall_fp32_tiles_match_the_oracle_and_the_model_tiling():
+    """PT_F_FP32_TALL puts the FP32 correction sweep on its 14-row tiles (the
+    tiling of the 511^3 runs) on a grid where the cost model picks 10 rows:
+    the mixed stage there is bitwise the stage on the model's tiling, and
+    within 1e-5 of the oracle's converged stage (ragged tiles: 30 = 2 x 12 + 6
+    rows, 40 columns in a 64-column tile)."""
+    nx, ny, nz = 40, 30, 22
+    assert not _fp32_tall_tiles(nx, ny, nz)
+    cfg = inputs.config_mixed(8)
+    import dataclasses
+    cfg = dataclasses.replace(cfg, nx=nx, ny=ny, nz=nz, name="forced-tall")
+    cfg.phys = cfg.phys.replace(lx=nx / 32, ly=ny / 32, lz=nz / 32)
+    f = inputs.initial_fields(cfg)
+    runs = {}
+    for tall in (False, True):
+        c = dataclasses.replace(cfg, phys=cfg.phys.replace(fp32_tall=tall))
+        g = _grid(c, f)
+        g.begin_step(False)
+        g.refresh(1.0, 1.0)
+        inner, outer, rho, ok = g.solve_mixed(1e-10, 1e-4, 400000, 60)
+        assert ok and outer >= 2
+        runs[tall] = (inner, outer, {name: g.get(name) for name in FIELDS})
+    assert runs[True][:2] == runs[False][:2]
+    for name in FIELDS:
+        assert np.array_equal(runs[True][2][name], runs[False][2][name]), name
+    o = oracle.Oracle(cfg.phys, nx, ny, nz, f["phi"], f["k0"])
+    o.begin_step()
+    o.refresh(1.0, 1.0)
+    _ito, rhoo = o.solve_linear(1e-10, 400000)
+    assert rhoo <= 1e-10
+    worst = {name: _rel(runs[True][2][name], o.f[name]) for name in FIELDS}
+    print(worst, flush=True)
+    assert max(worst.values()) <= 1e-5, worst
