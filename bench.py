@@ -116,11 +116,12 @@ def cpu_baseline(cfg, fields, ctx_n=255, single_n=64):
     }
 
 
-def time_to_tol(n: int, rtol: float = 1e-8, n_picard: int = 5, eta_in: float = 1e-4):
+def time_to_tol(n: int, rtol: float = 1e-8, n_picard: int = 5, eta_in: float = 1e-4, modes=("fp64", "mixed")):
     """Wall time of one physical step of the Picard schedule (n_picard stages,
     each linear solve to a relative residual rtol) on the mixed workload at n^3:
     FP64 PT sweeps against FP32 sweeps inside FP64 defect correction, on the
-    same GPU, from the same initial state."""
+    same GPU, from the same initial state (n_picard = 1: the step's first
+    stage alone; modes: either or both)."""
     import numpy as np
     import torch
     from paper_2207_08716_amd import inputs, schedules
@@ -140,10 +141,11 @@ def time_to_tol(n: int, rtol: float = 1e-8, n_picard: int = 5, eta_in: float = 1
     del w
 
     chunk, max_fp64, max_outer = 20000, 1_000_000, 40
+    what = "one Picard step" if n_picard == 5 else f"the first {n_picard} Picard stage(s) of a step"
     out = {"n": n, "rtol": rtol, "picard_stages": n_picard, "eta_in": eta_in,
-           "dt": cfg.phys.dt, "workload": f"{n}^3 two-anomaly grid, lognormal k0, DP cap; one Picard step"}
+           "dt": cfg.phys.dt, "workload": f"{n}^3 two-anomaly grid, lognormal k0, DP cap; {what}"}
     fields = {}
-    for mode in ("fp64", "mixed"):
+    for mode in modes:
         g = schedules.make_grid(cfg, f)
         if mode == "mixed":
             g.enable_mixed()
@@ -186,12 +188,13 @@ def time_to_tol(n: int, rtol: float = 1e-8, n_picard: int = 5, eta_in: float = 1
         g.close()
         del g
         torch.cuda.empty_cache()
-    out["speedup_mixed_vs_fp64"] = round(out["fp64_s"] / out["mixed_s"], 3)
-    rel = {}
-    for k in fields["fp64"]:
-        a, b = fields["mixed"][k], fields["fp64"][k]
-        rel[k] = float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
-    out["mixed_vs_fp64_rel_field_diff"] = rel
+    if "fp64" in fields and "mixed" in fields:
+        out["speedup_mixed_vs_fp64"] = round(out["fp64_s"] / out["mixed_s"], 3)
+        rel = {}
+        for k in fields["fp64"]:
+            a, b = fields["mixed"][k], fields["fp64"][k]
+            rel[k] = float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+        out["mixed_vs_fp64_rel_field_diff"] = rel
     return out
 
 
@@ -269,6 +272,10 @@ def main(argv=None):
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--ttt-n", type=int, default=127,
                     help="grid size of the mixed-vs-FP64 time-to-tolerance comparison (0: skip)")
+    ap.add_argument("--ttt-stages", type=int, default=5, help="Picard stages of the time-to-tolerance run")
+    ap.add_argument("--ttt-modes", default="fp64,mixed", help="solvers of the time-to-tolerance run")
+    ap.add_argument("--skip-sweeps", action="store_true",
+                    help="only the time-to-tolerance (and adjoint) measurements, no T_eff line")
     ap.add_argument("--adjoint-n", type=int, default=0,
                     help="grid size of the run-adjoint measurement, 10 steps x 5 stages (0: skip)")
     ap.add_argument("--adjoint-steps", type=int, default=10, help="physical steps of the adjoint run")
@@ -290,6 +297,13 @@ def main(argv=None):
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         return 1
+
+    if args.skip_sweeps:
+        rec = {"time_to_tol": (time_to_tol(args.ttt_n, n_picard=args.ttt_stages,
+                                           modes=tuple(args.ttt_modes.split(",")))
+                               if args.ttt_n > 0 else None)}
+        print(json.dumps(rec), flush=True)
+        return 0
 
     n = args.n
     if args.workload == "anomaly":
@@ -416,7 +430,8 @@ def main(argv=None):
     del g
     torch.cuda.empty_cache()
 
-    out["time_to_tol"] = time_to_tol(args.ttt_n) if args.ttt_n > 0 else None
+    out["time_to_tol"] = (time_to_tol(args.ttt_n, n_picard=args.ttt_stages, modes=tuple(args.ttt_modes.split(",")))
+                          if args.ttt_n > 0 else None)
     if args.adjoint_n > 0:
         out["adjoint_run"] = adjoint_measure(args.adjoint_n, args.adjoint_steps, args.adjoint_stages,
                                              checkpoint=args.adjoint_checkpoint, mixed=args.adjoint_mixed)

@@ -322,8 +322,10 @@ pt_status pt_picard_step(pt_grid* g, int32_t update_history, int32_t n_picard, d
 
 /* ---- Mixed precision (FP32 sweeps inside FP64 defect correction) --------
  * FP32 workspace for the correction system: query the size (24 FP32 padded
- * boxes), then bind a device buffer (256-byte aligned) of at least that many
- * bytes.  The library clears it before first use. */
+ * boxes, each pt_field_elems() + 64 floats apart), then bind a device buffer
+ * (256-byte aligned) of at least that many bytes.  The library clears it
+ * before first use.  Boxes 16..20 hold the FP64 residual of pt_residual
+ * (f_x, f_y, f_z, r_Pt, r_Pf) in FP32, in the field layout. */
 pt_status pt_mixed_workspace_size(const pt_grid* g, size_t* bytes);
 pt_status pt_bind_mixed_workspace(pt_grid* g, void* dev_ptr, size_t bytes);
 
@@ -350,7 +352,8 @@ pt_status pt_solve_mixed(pt_grid* g, double rtol, double eta_in, int64_t max_inn
 /* ---- Adjoint of a linear Picard stage (gradient of a misfit) -------------
  * Misfit J = 1/2 sum_s (Pf(cell_s) - d_s)^2 over ns distinct sensor cells,
  * given as linear indices over the nx*ny*nz cells (x fastest).  FP64
- * workspace: query the size for a sensor capacity, then bind. */
+ * workspace (40 boxes, each pt_field_elems() + 32 doubles apart, and a
+ * sensor tail): query the size for a sensor capacity, then bind. */
 pt_status pt_adjoint_workspace_size(const pt_grid* g, int32_t max_sensors, size_t* bytes);
 pt_status pt_bind_adjoint_workspace(pt_grid* g, void* dev_ptr, size_t bytes, int32_t max_sensors);
 

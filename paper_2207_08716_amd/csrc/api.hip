@@ -284,8 +284,13 @@ constexpr int MX_NBOX = 24;
 constexpr int MX_RES = 16;
 
 int64_t mx_box(const pt_grid* g) { return g->geom.S * (int64_t)(g->geom.nz + 1); }
-size_t mx_needed(const pt_grid* g) { return (size_t)(MX_NBOX * mx_box(g)) * sizeof(float); }
-float* mx(pt_grid* g, int b) { return g->mws + (int64_t)b * mx_box(g); }
+// Workspace boxes follow each other at a stride of one box plus 256 bytes:
+// boxes a power of two apart (2^27 elements at 511^3) put the sweeps' many
+// streams on the same memory channels at the same moment (measured: the
+// fields of one skewed allocation sweep ~5 % faster than unskewed ones).
+int64_t mx_stride(const pt_grid* g) { return mx_box(g) + 64; }   // floats
+size_t mx_needed(const pt_grid* g) { return (size_t)(MX_NBOX * mx_stride(g)) * sizeof(float); }
+float* mx(pt_grid* g, int b) { return g->mws + (int64_t)b * mx_stride(g); }
 
 // The eight reduced norms and the domain flag (copied together).
 pt_status read_norms(pt_grid* g, pt_norms* out) {
@@ -846,7 +851,7 @@ struct MixedTarget {
 pt_status mixed_core(pt_grid* g, const MixedTarget& t, double rtol, double eta_in, int64_t max_inner,
                      int32_t max_outer, double& ref_v, double& ref_p, bool& ref_set, int& copy,
                      int64_t* inner_iters, int32_t* outer_iters, double* rho) {
-    const int64_t box_bytes = mx_box(g) * (int64_t)sizeof(float);
+    const int64_t box_bytes = mx_stride(g) * (int64_t)sizeof(float);
     MixedPtrs m = t.m;
     m.kc32 = mx(g, 21); m.mus32 = mx(g, 22); m.chi32 = mx(g, 23);
     hipError_t e = launch_prepare_mixed(g->geom, m, g->stream);
@@ -933,7 +938,7 @@ pt_status mixed_ready(pt_grid* g) {
     if (!g->mws) return fail(g, PT_EINVAL, "mixed workspace not bound");
     if (g->prm.flags & PT_F_MECHOFF) return fail(g, PT_EINVAL, "mixed precision does not support PT_F_MECHOFF");
     if (!g->mws_clean) {
-        hipError_t e = hipMemsetAsync(g->mws, 0, 16 * mx_box(g) * (int64_t)sizeof(float), g->stream);
+        hipError_t e = hipMemsetAsync(g->mws, 0, 16 * mx_stride(g) * (int64_t)sizeof(float), g->stream);
         if (e != hipSuccess) return hip_fail(g, e, "mixed workspace clear");
         g->mws_clean = true;
     }
@@ -975,13 +980,14 @@ constexpr int AD_RHS = 16, AD_CHI = 21, AD_LBAR = 22, AD_ETAB = 24, AD_SB = 25, 
               AD_SO = 32, AD_MXOLD = 38;
 // per recorded stage: V (3), Pt, Pf, incoming ln(1-phi), k/mu_f, eta_phi
 constexpr int TAPE_NBOX = 8;
+int64_t ad_stride(const pt_grid* g) { return mx_box(g) + 32; }   // doubles: one box + 256 bytes
 size_t ad_needed(const pt_grid* g, int32_t max_sensors) {
-    return (size_t)(AD_NBOX * mx_box(g) + 3 * (int64_t)max_sensors) * sizeof(double);
+    return (size_t)(AD_NBOX * ad_stride(g) + 3 * (int64_t)max_sensors) * sizeof(double);
 }
-double* ad(pt_grid* g, int b) { return g->aws + (int64_t)b * mx_box(g); }
-int64_t* ad_offs(pt_grid* g) { return reinterpret_cast<int64_t*>(g->aws + AD_NBOX * mx_box(g)); }
-double* ad_vals(pt_grid* g) { return g->aws + AD_NBOX * mx_box(g) + g->aws_sensors; }
-double* ad_seed(pt_grid* g) { return g->aws + AD_NBOX * mx_box(g) + 2 * (int64_t)g->aws_sensors; }
+double* ad(pt_grid* g, int b) { return g->aws + (int64_t)b * ad_stride(g); }
+int64_t* ad_offs(pt_grid* g) { return reinterpret_cast<int64_t*>(g->aws + AD_NBOX * ad_stride(g)); }
+double* ad_vals(pt_grid* g) { return g->aws + AD_NBOX * ad_stride(g) + g->aws_sensors; }
+double* ad_seed(pt_grid* g) { return g->aws + AD_NBOX * ad_stride(g) + 2 * (int64_t)g->aws_sensors; }
 
 // Sensor cells (linear indices over the nx*ny*nz cells, x fastest) to
 // padded-box offsets, with range and distinctness checks.
@@ -1040,7 +1046,7 @@ pt_status misfit_impl(pt_grid* g, const int64_t* sensors, int32_t ns, const doub
 // (0 or 1) holding lambda.
 pt_status transposed_solve(pt_grid* g, const double* kc, const double* mus, double rtol, int64_t max_iter,
                            int* lam_copy, int64_t* iters, double* rho) {
-    const int64_t box_bytes = mx_box(g) * (int64_t)sizeof(double);
+    const int64_t box_bytes = ad_stride(g) * (int64_t)sizeof(double);
     hipError_t e = hipMemsetAsync(ad(g, 0), 0, 16 * box_bytes, g->stream);
     if (e != hipSuccess) return hip_fail(g, e, "adjoint clear");
     const int64_t nb = norm_blocks(g->geom);
@@ -1100,10 +1106,10 @@ pt_status transposed_solve(pt_grid* g, const double* kc, const double* mus, doub
 // FP64.  lambda ends in copy 0.  Needs beta_d > 0 and the mixed workspace.
 pt_status mixed_transposed_solve(pt_grid* g, const double* lp, const double* kc, const double* eta,
                                  const double* mus, double rtol, double eta_in, int64_t max_iter, int64_t* iters) {
-    const int64_t box_bytes = mx_box(g) * (int64_t)sizeof(double);
+    const int64_t box_bytes = ad_stride(g) * (int64_t)sizeof(double);
     hipError_t e = hipMemsetAsync(ad(g, 0), 0, 8 * box_bytes, g->stream);
     if (e == hipSuccess)
-        e = hipMemsetAsync(g->mws, 0, 16 * mx_box(g) * (int64_t)sizeof(float), g->stream);
+        e = hipMemsetAsync(g->mws, 0, 16 * mx_stride(g) * (int64_t)sizeof(float), g->stream);
     if (e == hipSuccess)
         e = launch_adj_oldvalues(g->geom, g->coef, ad(g, AD_RHS + 3), ad(g, AD_RHS + 4), ad(g, AD_MXOLD),
                                  ad(g, AD_MXOLD + 1), g->stream);
@@ -1212,7 +1218,7 @@ pt_status pt_adjoint_stage(pt_grid* g, const int64_t* sensors, int32_t ns, const
     if (st != PT_OK) return st;
     std::vector<double> seed(ns);
     for (int32_t s = 0; s < ns; ++s) seed[s] = -resid[s];   // -xbar, xbar = dJ/dPf
-    const int64_t box_bytes = mx_box(g) * (int64_t)sizeof(double);
+    const int64_t box_bytes = ad_stride(g) * (int64_t)sizeof(double);
     hipError_t e = hipMemsetAsync(ad(g, AD_RHS), 0, 5 * box_bytes, g->stream);
     if (e == hipSuccess) e = upload_sync(ad_seed(g), seed.data(), ns * sizeof(double), g->stream);
     if (e == hipSuccess) e = launch_scatter(ad_seed(g), ad_offs(g), ns, ad(g, AD_RHS + 4), g->stream);
@@ -1375,7 +1381,7 @@ pt_status pt_adjoint_run(pt_grid* g, int32_t n_steps, int32_t n_picard, int32_t 
 
     // ---- reverse sweep ---------------------------------------------------------
     const int64_t box_bytes = box * (int64_t)sizeof(double);
-    e = hipMemsetAsync(ad(g, AD_RHS), 0, (AD_NBOX - AD_RHS) * box_bytes, g->stream);
+    e = hipMemsetAsync(ad(g, AD_RHS), 0, (AD_NBOX - AD_RHS) * ad_stride(g) * (int64_t)sizeof(double), g->stream);
     if (e == hipSuccess) e = hipMemsetAsync(grad_dev, 0, box_bytes, g->stream);
     std::vector<double> seed(ns);
     for (int32_t s = 0; s < ns; ++s) seed[s] = -resid[s];

@@ -15,6 +15,15 @@ import torch
 from . import abi
 
 
+# Stride skew of the mixed workspace's FP32 boxes (floats), as in ptporo.h.
+MIXED_BOX_SKEW = 64
+# Skew between consecutive field buffers of one grid (doubles): buffers a
+# power of two apart (1 GiB at 511^3) put the sweep's 27 streams on the same
+# memory channels at the same moment; one skewed allocation sweeps ~5 %
+# faster at 511^3 than separate buffers (thesis sweep 6.70 -> 6.36 ms).
+FIELD_SKEW = 32
+
+
 def field_extent(name, nx, ny, nz):
     """(z, y, x) extent of a field inside its padded box."""
     if name in ("vx", "rx", "fox"):
@@ -62,12 +71,22 @@ class Grid:
         box = (nz + 1, ny + 1, self.pitch)
         assert self.lib.pt_field_elems(self.h) == box[0] * box[1] * box[2]
         self.buf = {}
+        nel = box[0] * box[1] * box[2]
+        names = [(fid, name) for fid, name in enumerate(abi.FIELDS) if name != "k0" or self.k0field]
+        count = sum(2 if fid < abi.NPING else 1 for fid, _ in names)
+        stride = nel + FIELD_SKEW
         with torch.cuda.stream(self.stream):
-            for fid, name in enumerate(abi.FIELDS):
-                if name == "k0" and not self.k0field:
-                    continue
-                ncopy = 2 if fid < abi.NPING else 1
-                self.buf[name] = [torch.zeros(box, dtype=torch.float64, device=self.device) for _ in range(ncopy)]
+            # every field from one allocation, consecutive buffers one box and
+            # 256 bytes apart (base 256-byte aligned)
+            self.arena = torch.zeros(count * stride + 32, dtype=torch.float64, device=self.device)
+            base = (-self.arena.data_ptr() // 8) % 32
+            k = 0
+            for fid, name in names:
+                self.buf[name] = []
+                for _ in range(2 if fid < abi.NPING else 1):
+                    off = base + k * stride
+                    self.buf[name].append(self.arena[off:off + nel].view(box))
+                    k += 1
             nbytes = C.c_size_t()
             _check(self.lib, self.h, self.lib.pt_workspace_size(self.h, C.byref(nbytes)), "workspace_size")
             self.ws = torch.zeros((nbytes.value + 7) // 8, dtype=torch.float64, device=self.device)
@@ -254,9 +273,10 @@ class Grid:
     def residual_fields(self):
         """(fx, fy, fz, r_Pt, r_Pf) last written by residual(), as numpy."""
         box = (self.nz + 1) * (self.ny + 1) * self.pitch
+        stride = box + MIXED_BOX_SKEW          # the workspace's box stride (ptporo.h)
         out = []
         for b, name in enumerate(("vx", "vy", "vz", "pt", "pf")):
-            t = self.mws[(16 + b) * box:(17 + b) * box].view(self.nz + 1, self.ny + 1, self.pitch)
+            t = self.mws[(16 + b) * stride:(16 + b) * stride + box].view(self.nz + 1, self.ny + 1, self.pitch)
             ez, ey, ex = field_extent(name, self.nx, self.ny, self.nz)
             with torch.cuda.stream(self.stream):
                 out.append(t[:ez, :ey, :ex].double().cpu().numpy())

@@ -81,7 +81,8 @@ def test_driver_and_adjoint_entry_points_validate_on_the_host(lib):
         assert lib.pt_solve_linear(h, 1e-8, 10, C.byref(inner), C.byref(rho)) == -1
         # workspaces: sizes and binding checks
         sz = C.c_size_t()
-        assert lib.pt_mixed_workspace_size(h, C.byref(sz)) == 0 and sz.value == 24 * box // 2
+        elems = lib.pt_field_elems(h)
+        assert lib.pt_mixed_workspace_size(h, C.byref(sz)) == 0 and sz.value == 24 * (elems + 64) * 4
         assert lib.pt_bind_mixed_workspace(h, C.c_void_p(0x1008), sz.value) == -1
         assert lib.pt_adjoint_workspace_size(h, 0, C.byref(sz)) == -1
         assert lib.pt_adjoint_workspace_size(h, 16, C.byref(sz)) == 0 and sz.value >= 40 * box
