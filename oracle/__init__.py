@@ -31,6 +31,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
 SRC_PATH = os.path.join(_HERE, "oracle.c")
+SOURCES = (SRC_PATH, os.path.join(_HERE, "reactive.c"))
 
 NORM_NAMES = ("f", "rpt", "rpf", "dL", "dPt", "dPf", "dVz", "dV")
 
@@ -50,7 +51,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(LIB_PATH):
         tmp = LIB_PATH + ".tmp"
         cmd = ["gcc", "-std=gnu11", "-O2", "-ffp-contract=off", "-fno-fast-math",
-               "-fopenmp", "-fPIC", "-shared", "-o", tmp, SRC_PATH, "-lm"]
+               "-fopenmp", "-fPIC", "-shared", "-o", tmp, *SOURCES, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, LIB_PATH)
     return LIB_PATH
@@ -90,7 +91,7 @@ _lib = None
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH):
+        if not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < max(os.path.getmtime(f) for f in SOURCES):
             build()
         lib = C.CDLL(LIB_PATH)
         P = C.POINTER

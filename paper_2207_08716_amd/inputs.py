@@ -76,6 +76,38 @@ class Physics:
 
 
 @dataclass
+class WavePhysics:
+    """Non-dimensional parameters of the reactive porosity-wave model (thesis
+    article 3, eqs (8)-(10); the appendix reactive script's constants): the
+    scales of eqs (5)-(7) are 1 (k0/mu_f = eta = drho = g = 1)."""
+    lx: float = 12.5
+    ly: float = 12.5
+    lz: float = 50.0
+    phi0: float = 1e-2        # background porosity
+    k_muf0: float = 1.0       # k0 / mu_f
+    eta: float = 1.0          # bulk viscosity
+    rho_f: float = 0.5        # fluid density
+    rho_s: float = 1.5        # solid density (rho_s - rho_f = 1)
+    g: float = 1.0            # gravity
+    beta_d: float = 1e-3      # drained compressibility (Deborah number 1e-3)
+    beta_s: float = 1e-3 * 11.0 / 12.0   # solid compressibility without reaction
+    beta_f: float = 6e-3      # fluid compressibility
+    tau: float = 1e-2         # reaction time, 1/Da (Da = 100)
+    beta_x: float = -0.2      # d Xs_eq / d Pf (negative Clapeyron slope)
+    delta_x: float = 3.0      # solid density change with Xs
+    xs_max: float = 0.05      # largest volatile mass fraction of the solid
+    dt: float = 1e-6          # physical time step
+    c_pf: float = 16.1        # safety factor of the fluid-pressure pseudo step
+    phi_min: float = 1e-4     # porosity clamp
+    phi_max: float = 1.0
+    nup: int = 10             # iterations between pseudo-step refreshes / checks
+    eps: float = 2e-8         # stopping value of the one-iteration change
+
+    def replace(self, **kw) -> "WavePhysics":
+        return dataclasses.replace(self, **kw)
+
+
+@dataclass
 class Anomaly:
     centre: tuple          # (x, y, z) in physical units
     amp: float             # amplitude in units of phi0
@@ -280,6 +312,20 @@ def config_production(nx: int = 511, ny: int = 511, nz: int = 1022) -> Config:
                   noise_seed=None, mode="thesis", n_iter=1000)
 
 
+def config_reactive(n: int = 127, da: float = 100.0, nz: int | None = None) -> Config:
+    """Reactive porosity waves (article 3; the appendix reactive script): a
+    12.5 x 12.5 x 50 box on n x n x 4n cells, two vertically superposed
+    spherical Gaussian anomalies (radius 1.5; amplitudes 1.5 phi0 at z = 5
+    and 0.75 phi0 at z = 11.5, so the deeper one peaks at 2.5 %), Xs = Xs_max/2,
+    Pf = 0; Damkoehler number da (tau = 1/da), dt = 1e-6 for da >= 1, else
+    1e-5 (the paper's steps for its two Damkoehler numbers)."""
+    ph = WavePhysics(tau=1.0 / da, dt=1e-6 if da >= 1.0 else 1e-5)
+    nz = 4 * n if nz is None else nz
+    return Config(name=f"reactive{n}x{n}x{nz}", nx=n, ny=n, nz=nz, phys=ph,
+                  anomalies=[Anomaly((6.25, 6.25, 5.0), 1.5, 1.5), Anomaly((6.25, 6.25, 11.5), 0.75, 1.5)],
+                  noise_seed=None, mode="thesis")
+
+
 CONFIGS = {
     "parity": config_parity,
     "picard": config_fp64_picard,
@@ -287,6 +333,7 @@ CONFIGS = {
     "adjoint": config_adjoint,
     "waves": config_waves,
     "production": config_production,
+    "reactive": config_reactive,
 }
 
 
@@ -301,5 +348,6 @@ def initial_fields(cfg: Config) -> dict:
 
 __all__ = ["Physics", "Anomaly", "Config", "CONFIGS", "config_parity",
            "config_fp64_picard", "config_mixed", "config_adjoint", "config_waves", "config_production",
+           "config_reactive", "WavePhysics",
            "initial_fields", "porosity_field", "k0_field", "gaussian_random_field",
            "sensor_cells", "random_centres", "cell_centres", "PICARD_DT"]
