@@ -259,6 +259,72 @@ def adjoint_measure(n, n_steps=10, n_picard=5, rtol=1e-10, ns=64, checkpoint=Fal
     return out
 
 
+def reactive_measure(n: int, nz: int, da: float = 100.0, warm: int = 20, reps: int = 100,
+                     step_n: int = 127, step_cap: int = 50000):
+    """Reactive porosity waves (article 3) on n x n x nz cells: the PT
+    iteration's time (pseudo-step refresh and checks every nup included) over
+    `reps` iterations with HIP events on the solver's stream; and, on
+    step_n x step_n x 4 step_n cells, one physical step solved to the
+    script's stopping value from the initial state (the pseudo step shrinks
+    with h^2 while dt stays, so the iterations a step needs grow with the
+    resolution: about 10^4 at 506 x 506 x 2042)."""
+    import torch
+    from paper_2207_08716_amd import inputs
+    from paper_2207_08716_amd.waves import Waves
+    t0 = time.perf_counter()
+    cfg = inputs.config_reactive(n, da=da, nz=nz)
+    phi = inputs.porosity_field(cfg)
+    w = Waves(cfg.phys, cfg.nx, cfg.ny, cfg.nz, phi)
+    del phi
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    w.begin_step()
+    w.iterate(warm)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(w.stream)
+    w.iterate(reps)
+    e1.record(w.stream)
+    e1.synchronize()
+    t_it = e0.elapsed_time(e1) / 1e3 / reps
+    ncell = cfg.nx * cfg.ny * cfg.nz
+    # the paper's effective throughput counts 3 updated fields (read and
+    # written) and 1 known field; the sweep itself moves 4 iterated fields
+    # (read and written) and 3 old-step fields (read)
+    a_paper = (2 * 3 + 1) * ncell * 8
+    a_alg = (2 * 4 + 3) * ncell * 8
+    w.close()
+    del w
+    torch.cuda.empty_cache()
+    step = None
+    if step_n > 0:
+        scfg = inputs.config_reactive(step_n, da=da)
+        ws = Waves(scfg.phys, scfg.nx, scfg.ny, scfg.nz, inputs.porosity_field(scfg))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ws.begin_step()
+        iters, err, ok = ws.solve_step(scfg.phys.eps, step_cap)
+        t_step = time.perf_counter() - t1
+        ws.close()
+        del ws
+        step = {"grid": f"{scfg.nx}x{scfg.ny}x{scfg.nz}", "iterations": iters, "stopping_value": err,
+                "converged": bool(ok), "eps": scfg.phys.eps, "s": round(t_step, 3)}
+    return {
+        "workload": (f"{cfg.nx}x{cfg.ny}x{cfg.nz} reactive porosity waves (12.5x12.5x50 box, two Gaussian "
+                     f"anomalies, Da={da:g}, dt={cfg.phys.dt:g}, pseudo step and checks every {cfg.phys.nup})"),
+        "cells": ncell, "precision": "fp64",
+        "t_it_ms": round(t_it * 1e3, 4),
+        "t_eff_gbs": round(a_paper / t_it / 1e9, 2),
+        "t_eff_definition": "(2*3+1)*cells*8 bytes per iteration",
+        "roofline": {"bound": "hbm", "kernel": "k_waves_sweep (plus its pseudo-step and check kernels)",
+                     "achieved": round(a_alg / t_it / 1e9, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(a_alg / t_it / 1e9 / HBM_PEAK_GBS, 4),
+                     "algorithmic_bytes_per_launch": a_alg},
+        "physical_step": step,
+        "setup_s": round(t_setup, 1),
+    }
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -275,7 +341,12 @@ def main(argv=None):
     ap.add_argument("--ttt-stages", type=int, default=5, help="Picard stages of the time-to-tolerance run")
     ap.add_argument("--ttt-modes", default="fp64,mixed", help="solvers of the time-to-tolerance run")
     ap.add_argument("--skip-sweeps", action="store_true",
-                    help="only the time-to-tolerance (and adjoint) measurements, no T_eff line")
+                    help="only the reactive-wave and time-to-tolerance measurements, no T_eff line")
+    ap.add_argument("--reactive-n", type=int, default=506,
+                    help="reactive porosity-wave measurement on n x n x reactive-nz cells (0: off)")
+    ap.add_argument("--reactive-nz", type=int, default=2042)
+    ap.add_argument("--reactive-step-n", type=int, default=127,
+                    help="grid (n x n x 4n) of the reactive physical-step measurement (0: off)")
     ap.add_argument("--adjoint-n", type=int, default=0,
                     help="grid size of the run-adjoint measurement, 10 steps x 5 stages (0: skip)")
     ap.add_argument("--adjoint-steps", type=int, default=10, help="physical steps of the adjoint run")
@@ -299,7 +370,10 @@ def main(argv=None):
         return 1
 
     if args.skip_sweeps:
-        rec = {"time_to_tol": (time_to_tol(args.ttt_n, n_picard=args.ttt_stages,
+        rec = {"reactive_waves": (reactive_measure(args.reactive_n, args.reactive_nz,
+                                                   step_n=args.reactive_step_n)
+                                  if args.reactive_n > 0 else None),
+               "time_to_tol": (time_to_tol(args.ttt_n, n_picard=args.ttt_stages,
                                            modes=tuple(args.ttt_modes.split(",")))
                                if args.ttt_n > 0 else None)}
         print(json.dumps(rec), flush=True)
@@ -430,6 +504,8 @@ def main(argv=None):
     del g
     torch.cuda.empty_cache()
 
+    out["reactive_waves"] = (reactive_measure(args.reactive_n, args.reactive_nz, step_n=args.reactive_step_n)
+                             if args.reactive_n > 0 else None)
     out["time_to_tol"] = (time_to_tol(args.ttt_n, n_picard=args.ttt_stages, modes=tuple(args.ttt_modes.split(",")))
                           if args.ttt_n > 0 else None)
     if args.adjoint_n > 0:

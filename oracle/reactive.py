@@ -92,15 +92,17 @@ class ReactiveOracle:
         self.lib.rw_begin_step(self.ctx, C.byref(self._st))
         self.iter = 0
 
-    def iterate(self, n):
+    def iterate(self, n, dtau=None):
         """n PT iterations continuing the step's count: the pseudo step
         before iterations with iter % nup == 1, the error after iterations
-        with iter % nup == 0 (returned, last one)."""
+        with iter % nup == 0 (returned, last one).  dtau, if given, replaces
+        the pseudo step the state would give (a window of a larger grid
+        takes the full grid's)."""
         nup = self.phys.nup
         for _ in range(n):
             it = self.iter + 1
             if (it - 1) % nup == 0:
-                self.dtau = float(self.lib.rw_dtau(self.ctx, C.byref(self._st)))
+                self.dtau = float(self.lib.rw_dtau(self.ctx, C.byref(self._st))) if dtau is None else float(dtau)
             err = C.c_double()
             want = it % nup == 0
             self.lib.rw_iteration(self.ctx, C.byref(self._st), self.dtau, C.byref(err) if want else None)

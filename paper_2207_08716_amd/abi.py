@@ -1,4 +1,5 @@
-"""ctypes declarations of the C ABI in include/ptporo.h (marshalling only)."""
+"""ctypes declarations of the C ABI in include/ptporo.h and include/ptwaves.h
+(marshalling only)."""
 from __future__ import annotations
 
 import ctypes as C
@@ -59,6 +60,28 @@ EXPORTS = ["pt_create", "pt_destroy", "pt_field_elems", "pt_bind_field", "pt_wor
            "pt_picard_step", "pt_mixed_workspace_size", "pt_bind_mixed_workspace", "pt_residual",
            "pt_solve_mixed", "pt_adjoint_workspace_size", "pt_bind_adjoint_workspace", "pt_set_log_k0",
            "pt_misfit", "pt_adjoint_stage", "pt_adjoint_tape_size", "pt_adjoint_run", "pt_copy", "pt_status_str", "pt_last_error", "pt_abi_version"]
+
+# Reactive porosity waves (include/ptwaves.h).
+WAVES_ABI_VERSION = 1
+WAVES_FIELDS = ("xs", "pf", "phi", "dpfdt", "xs_old", "pf_old", "phi_old")
+WAVES_FIELD_ID = {n: i for i, n in enumerate(WAVES_FIELDS)}
+WAVES_NPING = 4
+
+
+class WavesParams(C.Structure):
+    _fields_ = [("version", C.c_int32), ("nup", C.c_int32),
+                ("lx", C.c_double), ("ly", C.c_double), ("lz", C.c_double),
+                ("phi0", C.c_double), ("k_muf0", C.c_double), ("eta", C.c_double),
+                ("rho_f", C.c_double), ("rho_s", C.c_double), ("g", C.c_double),
+                ("beta_d", C.c_double), ("beta_s", C.c_double), ("beta_f", C.c_double),
+                ("tau", C.c_double), ("beta_x", C.c_double), ("delta_x", C.c_double), ("xs_max", C.c_double),
+                ("dt", C.c_double), ("c_pf", C.c_double), ("phi_min", C.c_double), ("phi_max", C.c_double)]
+
+
+WAVES_EXPORTS = ["pt_waves_create", "pt_waves_destroy", "pt_waves_field_elems", "pt_waves_bind_field",
+                 "pt_waves_workspace_size", "pt_waves_bind_workspace", "pt_waves_set_stream", "pt_waves_current",
+                 "pt_waves_begin_step", "pt_waves_iterate", "pt_waves_last_error", "pt_waves_solve_step",
+                 "pt_waves_last_message"]
 
 PROGRESS_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int64)
 PROGRESS_PHASE = {0: "forward", 1: "reverse", 2: "recompute", 3: "stage"}
@@ -137,6 +160,24 @@ def load(path: str = LIB_PATH):
     for name in EXPORTS:
         if name not in ("pt_status_str", "pt_last_error", "pt_field_elems", "pt_abi_version"):
             getattr(lib, name).restype = C.c_int
+    lib.pt_waves_create.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_int64, P(WavesParams), P(vp)]
+    lib.pt_waves_destroy.argtypes = [vp]
+    lib.pt_waves_field_elems.argtypes = [vp]
+    lib.pt_waves_field_elems.restype = C.c_int64
+    lib.pt_waves_bind_field.argtypes = [vp, C.c_int32, C.c_int32, vp]
+    lib.pt_waves_workspace_size.argtypes = [vp, P(C.c_size_t)]
+    lib.pt_waves_bind_workspace.argtypes = [vp, vp, C.c_size_t]
+    lib.pt_waves_set_stream.argtypes = [vp, vp]
+    lib.pt_waves_current.argtypes = [vp, C.c_int32, P(C.c_int32)]
+    lib.pt_waves_begin_step.argtypes = [vp]
+    lib.pt_waves_iterate.argtypes = [vp, C.c_int64]
+    lib.pt_waves_last_error.argtypes = [vp, P(C.c_double)]
+    lib.pt_waves_solve_step.argtypes = [vp, C.c_double, C.c_int64, P(C.c_int64), P(C.c_double)]
+    lib.pt_waves_last_message.argtypes = [vp]
+    lib.pt_waves_last_message.restype = C.c_char_p
+    for name in WAVES_EXPORTS:
+        if name not in ("pt_waves_field_elems", "pt_waves_last_message"):
+            getattr(lib, name).restype = C.c_int
     if lib.pt_abi_version() != ABI_VERSION:
         raise ImportError("libptporo.so ABI version mismatch")
     _lib = lib
@@ -165,4 +206,14 @@ def params_from(phys, k0field: bool) -> Params:
         if ctype is C.c_double:
             setattr(p, name, float(getattr(phys, name)))
     p.nup = int(phys.nup)
+    return p
+
+
+def waves_params_from(phys) -> WavesParams:
+    """Marshal a WavePhysics record into the C struct."""
+    p = WavesParams()
+    p.version = WAVES_ABI_VERSION
+    p.nup = int(phys.nup)
+    for name, ctype in WavesParams._fields_[2:]:
+        setattr(p, name, float(getattr(phys, name)))
     return p

@@ -3,6 +3,13 @@
   python -m paper_2207_08716_amd.profiling trace <kernel_stats.csv> <out.md> <command...>
   python -m paper_2207_08716_amd.profiling traffic <fetch_counter_collection.csv>
         <write_counter_collection.csv> <n> <out.json> <out.md> <command...>
+  python -m paper_2207_08716_amd.profiling traffic-waves <fetch_counter_collection.csv>
+        <write_counter_collection.csv> <nx> <ny> <nz> <out.json> <out.md> <command...>
+
+The first form covers the two-phase thesis sweep on an n^3 grid (A_eff =
+25 N 8 bytes), the second the reactive porosity-wave sweep on nx x ny x nz
+cells (4 iterated fields read and written and 3 old-step fields read:
+11 N 8 bytes).
 
 FETCH_SIZE and WRITE_SIZE are read in KiB per dispatch and calibrated with the
 streaming copy kernel of known size that the benchmark runs in the same
@@ -47,11 +54,12 @@ def _per_kernel(path):
     return {k: sum(v) / len(v) for k, v in acc.items()}
 
 
-def traffic_summary(fetch_csv, write_csv, n, out_json, out_md, command, copy_elems=None):
+def traffic_summary(fetch_csv, write_csv, n, out_json, out_md, command, copy_elems=None,
+                    dominant=DOMINANT, a_eff=None, kernel_src=KERNEL_SRC, grid=None):
     fetch = _per_kernel(fetch_csv)
     write = _per_kernel(write_csv)
     copy_key = next(k for k in fetch if COPY in k)
-    dom_key = next(k for k in fetch if DOMINANT in k)
+    dom_key = next(k for k in fetch if dominant in k)
     # the benchmark copies one padded field box: (n+1)^2 * pitch doubles
     pitch = ((n + 1 + 31) // 32) * 32
     copy_bytes = (copy_elems or (n + 1) * (n + 1) * pitch) * 8
@@ -59,9 +67,9 @@ def traffic_summary(fetch_csv, write_csv, n, out_json, out_md, command, copy_ele
     w_fac = copy_bytes / (write[copy_key] * 1024.0)
     fb = fetch[dom_key] * 1024.0 * f_fac
     wb = write[dom_key] * 1024.0 * w_fac
-    a_eff = 25.0 * n ** 3 * 8
-    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
-    rec = {"n": n, "kernel": dom_key, "kernel_source_sha": sha,
+    a_eff = 25.0 * n ** 3 * 8 if a_eff is None else float(a_eff)
+    sha = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()[:16]
+    rec = {"n": n, "grid": grid or f"{n}^3", "kernel": dom_key, "kernel_source_sha": sha,
            "fetch_bytes": fb, "write_bytes": wb, "bytes_per_launch": fb + wb,
            "fetch_factor": f_fac, "write_factor": w_fac, "a_eff_bytes": a_eff,
            "command": command}
@@ -77,7 +85,8 @@ def traffic_summary(fetch_csv, write_csv, n, out_json, out_md, command, copy_ele
             lines.append(f"| {k} | {fetch[k]:.0f} | {write[k]:.0f} | {fetch[k] * 1024 * f_fac / 1e9:.3f} | "
                          f"{write[k] * 1024 * w_fac / 1e9:.3f} |")
     lines += ["", f"Dominant kernel {dom_key}: {(fb + wb) / 1e9:.3f} GB per launch against "
-              f"A_eff = {a_eff / 1e9:.3f} GB (ratio {(fb + wb) / a_eff:.3f}); kernel source sha {sha}."]
+              f"{a_eff / 1e9:.3f} GB of algorithmic bytes (ratio {(fb + wb) / a_eff:.3f}); "
+              f"kernel source sha {sha}."]
     open(out_md, "w").write("\n".join(lines) + "\n")
 
 
@@ -88,5 +97,12 @@ if __name__ == "__main__":
     elif what == "traffic":
         traffic_summary(sys.argv[2], sys.argv[3], int(sys.argv[4]), sys.argv[5], sys.argv[6],
                         " ".join(sys.argv[7:]))
+    elif what == "traffic-waves":
+        nx, ny, nz = (int(v) for v in sys.argv[4:7])
+        pitch = ((nx + 1 + 31) // 32) * 32
+        traffic_summary(sys.argv[2], sys.argv[3], nx, sys.argv[7], sys.argv[8], " ".join(sys.argv[9:]),
+                        copy_elems=(nz + 1) * (ny + 1) * pitch, dominant="k_waves_sweep<false>",
+                        a_eff=11 * nx * ny * nz * 8, grid=f"{nx}x{ny}x{nz}",
+                        kernel_src=os.path.join(ROOT, "paper_2207_08716_amd", "csrc", "waves.hip"))
     else:
         raise SystemExit(__doc__)

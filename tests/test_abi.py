@@ -11,8 +11,8 @@ from paper_2207_08716_amd import abi, inputs
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def _declared():
-    text = open(os.path.join(ROOT, "include", "ptporo.h")).read()
+def _declared(header="ptporo.h"):
+    text = open(os.path.join(ROOT, "include", header)).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(pt_[a-z_0-9]+)\s*\(", text)))
 
@@ -30,6 +30,51 @@ def test_every_declared_symbol_is_exported(lib):
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(abi.EXPORTS)
+
+
+def test_every_waves_symbol_is_exported(lib):
+    names = _declared("ptwaves.h")
+    assert "pt_waves_iterate" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(abi.WAVES_EXPORTS)
+
+
+def test_waves_entry_points_validate_on_the_host(lib):
+    ph = inputs.WavePhysics()
+    p = abi.waves_params_from(ph)
+    h = C.c_void_p()
+    assert lib.pt_waves_create(1, 4, 4, 32, C.byref(p), C.byref(h)) == -1
+    assert lib.pt_waves_create(4, 4, 4, 4, C.byref(p), C.byref(h)) == -1     # pitch < nx + 1
+    for bad in (dict(dt=0.0), dict(tau=-1.0), dict(phi_min=0.0), dict(phi_max=1.5), dict(xs_max=1.0),
+                dict(c_pf=float("nan")), dict(nup=0)):
+        q = abi.waves_params_from(ph.replace(**bad))
+        assert lib.pt_waves_create(4, 4, 4, 32, C.byref(q), C.byref(h)) == -1, bad
+    q = abi.waves_params_from(ph)
+    q.version = 7
+    assert lib.pt_waves_create(4, 4, 4, 32, C.byref(q), C.byref(h)) == -1
+    assert lib.pt_waves_create(4, 5, 6, 32, C.byref(p), C.byref(h)) == 0
+    try:
+        assert lib.pt_waves_field_elems(h) == 7 * 6 * 32
+        assert lib.pt_waves_bind_field(h, 0, 0, C.c_void_p(0x1008)) == -1
+        assert lib.pt_waves_bind_field(h, 9, 0, C.c_void_p(0x1000)) == -1
+        assert lib.pt_waves_bind_field(h, abi.WAVES_FIELD_ID["pf_old"], 1, C.c_void_p(0x1000)) == -1
+        assert b"copy" in lib.pt_waves_last_message(h)
+        # nothing bound: every launching call refuses before touching the device
+        assert lib.pt_waves_begin_step(h) == -1
+        assert lib.pt_waves_iterate(h, 1) == -1
+        assert b"bound" in lib.pt_waves_last_message(h)
+        it, e = C.c_int64(), C.c_double()
+        assert lib.pt_waves_solve_step(h, 1e-8, 100, C.byref(it), C.byref(e)) == -1
+        assert lib.pt_waves_solve_step(h, 0.0, 100, C.byref(it), C.byref(e)) == -1
+        assert lib.pt_waves_last_error(h, C.byref(e)) == -1              # nothing computed yet
+        sz = C.c_size_t()
+        assert lib.pt_waves_workspace_size(h, C.byref(sz)) == 0 and sz.value > 0
+        assert lib.pt_waves_bind_workspace(h, C.c_void_p(0x1000), 8) == -1
+        cp = C.c_int32()
+        assert lib.pt_waves_current(h, abi.WAVES_FIELD_ID["pf"], C.byref(cp)) == 0 and cp.value == 0
+    finally:
+        lib.pt_waves_destroy(h)
 
 
 def test_create_validates_arguments(lib):
