@@ -307,18 +307,72 @@ typedef struct {
 pt_status pt_get_counters(const pt_grid* g, pt_counters* out);
 pt_status pt_set_counters(pt_grid* g, const pt_counters* in);
 
+/* Stage solvers of pt_picard_step. */
+#define PT_SOLVER_FP64 0    /* pt_solve_linear                               */
+#define PT_SOLVER_MIXED 1   /* pt_solve_mixed (FP32 sweeps, FP64 correction) */
+#define PT_SOLVER_MG 2      /* pt_solve_mg (geometric multigrid V-cycles)    */
+
 /* One physical step of the Picard schedule (the thesis's M-P driver): the
  * step set-up of pt_begin_step(update_history), then n_picard stages of
  * { refresh without relaxation (eqs (23)-(26)); linear solve of the frozen
- * system to the relative residual rtol (pt_solve_linear; or, with mixed,
- * pt_solve_mixed with inner tolerance eta_in and at most 64 corrections,
- * max_iter sweeps per correction); porosity step of eq (22) }.  sweeps: PT
- * sweeps of all stages (FP64 or FP32); rho: the largest final relative
- * residual.  Synchronises.  PT_ENOTCONV: a stage missed rtol within its
- * limits; the step stops there with a valid state.  The mixed form needs the
- * mixed workspace. */
+ * system to the relative residual rtol by the solver `mixed` (PT_SOLVER_*):
+ * pt_solve_linear; pt_solve_mixed with inner tolerance eta_in and at most
+ * 64 corrections, max_iter sweeps per correction; or pt_solve_mg with at
+ * most max_iter V-cycles; porosity step of eq (22) }.  sweeps: PT sweeps of
+ * all stages (FP64 or FP32), V-cycles for the multigrid solver; rho: the
+ * largest final relative residual.  Synchronises.  PT_ENOTCONV: a stage
+ * missed rtol within its limits; the step stops there with a valid state.
+ * The mixed and multigrid forms need their workspaces. */
 pt_status pt_picard_step(pt_grid* g, int32_t update_history, int32_t n_picard, double rtol, int64_t max_iter,
                          int32_t mixed, double eta_in, int64_t* sweeps, double* rho);
+
+/* ---- Geometric multigrid for the linear Picard stage -------------------
+ * The thesis's outlook (concluding chapter, future work): geometric
+ * multigrid over the PT iteration, which without damping is a weighted
+ * Jacobi iteration.  Correction scheme, V-cycles.  Each coarse grid has
+ * ceil(n/2) cells per axis on the same domain (odd counts give grids that
+ * are not nested); transfers interpolate linearly between the grids' cell
+ * centres and faces per staggering, restriction being the transpose with
+ * rows normalised.  Smoother: nu1 / nu2 linear PT sweeps before / after the
+ * coarse correction, without damping and without the numerical
+ * compressibility beta_n (neither changes the solution), with pseudo steps
+ * rho_i h^2 / (c_v mu_s), mu_s / n_pt and h^2 (1 + beta_d B/alpha) /
+ * (c_pf k_loc).  Coarsest grid: coarse_sweeps damped PT sweeps with the
+ * handle's parameters.  Coarse operators: the same discretisation with
+ * k/mu_f averaged harmonically and eta_phi, mu_s, ln(1-phi) arithmetically
+ * over the finer grid; the coarse right-hand side sits in the coarse
+ * grid's Fo and old-pressure fields.  Needs beta_d > 0 and alpha B != 1. */
+#define PT_MG_MAX_LEVELS 12
+typedef struct {
+    int32_t version;          /* PT_ABI_VERSION                                      */
+    int32_t levels;           /* grids including the fine one, 2..PT_MG_MAX_LEVELS;
+                                 0: coarsen until an axis has at most 8 cells        */
+    int32_t nu1, nu2;         /* smoothing sweeps before (>= 1) and after (>= 0)     */
+    int32_t coarse_sweeps;    /* damped PT sweeps on the coarsest grid (>= 1)        */
+    int32_t n_pt;             /* the smoother's Pt pseudo step mu_s / n_pt (>= 1)    */
+    double c_v, c_pf;         /* the smoother's pseudo-step factors                  */
+} pt_mg_params;
+
+/* Workspace of a hierarchy (the fine grid's FP32 residual, and per coarse
+ * grid 25 FP64 boxes plus, above the coarsest, 5 FP32 boxes: about a
+ * quarter of the fine grid's fields): query, then bind a device buffer
+ * (256-byte aligned) of at least that size; binding clears it (enqueued).
+ * PT_EINVAL if the grid cannot be coarsened to the requested levels. */
+pt_status pt_mg_workspace_size(const pt_grid* g, const pt_mg_params* mg, size_t* bytes);
+pt_status pt_bind_mg_workspace(pt_grid* g, const pt_mg_params* mg, void* dev_ptr, size_t bytes);
+/* The bound hierarchy: levels (0 if none) and, if counts is not NULL, the
+ * cell counts nx, ny, nz of each grid (3 * levels values). */
+pt_status pt_mg_levels(const pt_grid* g, int32_t* levels, int32_t* counts);
+
+/* One linear Picard stage (coefficients and porosity frozen, as
+ * pt_solve_linear) by multigrid: repeat { nu1 smoothing sweeps; residual of
+ * the state in FP64 and rho as in pt_solve_linear (same step reference; if
+ * the step has none, the residual of the starting state sets it); stop when
+ * rho <= rtol or after max_cycles coarse corrections; coarse-grid
+ * correction; nu2 sweeps }.  cycles: coarse corrections done.
+ * Synchronises once per cycle.  PT_ENOTCONV if rtol is not met (the state
+ * is valid; calling again continues). */
+pt_status pt_solve_mg(pt_grid* g, double rtol, int64_t max_cycles, int64_t* cycles, double* rho);
 
 /* ---- Mixed precision (FP32 sweeps inside FP64 defect correction) --------
  * FP32 workspace for the correction system: query the size (24 FP32 padded

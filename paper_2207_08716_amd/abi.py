@@ -59,7 +59,23 @@ EXPORTS = ["pt_create", "pt_destroy", "pt_field_elems", "pt_bind_field", "pt_wor
            "pt_porosity_step", "pt_reset_state", "pt_set_porosity", "pt_get_counters", "pt_set_counters",
            "pt_picard_step", "pt_mixed_workspace_size", "pt_bind_mixed_workspace", "pt_residual",
            "pt_solve_mixed", "pt_adjoint_workspace_size", "pt_bind_adjoint_workspace", "pt_set_log_k0",
-           "pt_misfit", "pt_adjoint_stage", "pt_adjoint_tape_size", "pt_adjoint_run", "pt_copy", "pt_status_str", "pt_last_error", "pt_abi_version"]
+           "pt_misfit", "pt_adjoint_stage", "pt_adjoint_tape_size", "pt_adjoint_run", "pt_copy", "pt_status_str", "pt_last_error", "pt_abi_version",
+           "pt_mg_workspace_size", "pt_bind_mg_workspace", "pt_mg_levels", "pt_solve_mg"]
+
+# Stage solvers of pt_picard_step and the multigrid hierarchy.
+SOLVER_FP64, SOLVER_MIXED, SOLVER_MG = 0, 1, 2
+MG_MAX_LEVELS = 12
+
+
+class MgParams(C.Structure):
+    _fields_ = [("version", C.c_int32), ("levels", C.c_int32), ("nu1", C.c_int32), ("nu2", C.c_int32),
+                ("coarse_sweeps", C.c_int32), ("n_pt", C.c_int32), ("c_v", C.c_double), ("c_pf", C.c_double)]
+
+
+def mg_params(levels=0, nu1=4, nu2=4, coarse_sweeps=100, n_pt=4, c_v=6.1, c_pf=6.1) -> MgParams:
+    return MgParams(ABI_VERSION, int(levels), int(nu1), int(nu2), int(coarse_sweeps), int(n_pt),
+                    float(c_v), float(c_pf))
+
 
 # Reactive porosity waves (include/ptwaves.h).
 WAVES_ABI_VERSION = 1
@@ -152,6 +168,10 @@ def load(path: str = LIB_PATH):
     lib.pt_adjoint_run.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_int64,
                                    P(C.c_int64), C.c_int32, P(C.c_double), vp, C.c_size_t, vp,
                                    P(C.c_double), P(C.c_int64), P(C.c_int64)]
+    lib.pt_mg_workspace_size.argtypes = [vp, P(MgParams), P(C.c_size_t)]
+    lib.pt_bind_mg_workspace.argtypes = [vp, P(MgParams), vp, C.c_size_t]
+    lib.pt_mg_levels.argtypes = [vp, P(C.c_int32), P(C.c_int32)]
+    lib.pt_solve_mg.argtypes = [vp, C.c_double, C.c_int64, P(C.c_int64), P(C.c_double)]
     lib.pt_status_str.argtypes = [C.c_int]
     lib.pt_status_str.restype = C.c_char_p
     lib.pt_last_error.argtypes = [vp]

@@ -40,6 +40,12 @@ struct pt_grid {
     double dts = 0.0;          // PT_F_DTS_RULE: the present stress-history step
     pt_progress_fn progress = nullptr;   // per-stage report of long calls
     void* progress_user = nullptr;
+    double* gws = nullptr;     // multigrid workspace
+    size_t gws_bytes = 0;
+    pt_mg_params mgp{};        // multigrid parameters of the bound workspace
+    int mg_levels = 0;         // grids of the hierarchy, the fine one included
+    Geom mg_geom[PT_MG_MAX_LEVELS];
+    int mg_cur[PT_MG_MAX_LEVELS] = {};   // present copy of the coarse grids' iterated fields
     std::string err;
 };
 
@@ -1138,11 +1144,377 @@ pt_status mixed_transposed_solve(pt_grid* g, const double* lp, const double* kc,
                       &rho);
 }
 }  // namespace
+}  // extern "C"
+
+namespace {
+
+// ---- geometric multigrid for the linear Picard stage ------------------------
+// Correction scheme with V-cycles.  Every grid runs the library's own sweeps:
+// the smoother is the linear PT sweep without damping and without the
+// numerical compressibility (a weighted Jacobi iteration; neither term
+// changes the solution), with the Pt pseudo step mu_s / n_pt; the coarsest
+// grid runs the damped PT sweep.  A coarse grid (ceil(n/2) cells per axis,
+// same domain) holds the correction e of its finer grid and solves
+// A e = -R r, the restricted residual of the finer grid, written into the
+// grid's constant terms: the face fields Fo (momentum) and the old pressures
+// (whose terms in r_Pt and r_Pf are linear), with the physical constants
+// (buoyancy, background shear) set to zero so that the residual at e = 0 is
+// exactly R r.  Coefficients (k/mu_f harmonically, eta_phi, mu_s and
+// ln(1-phi) arithmetically) are averaged down at each solve.
+//
+// Workspace (doubles, boxes a box plus 256 bytes apart): the fine grid's FP32
+// residual (5 boxes); per-block maxima of the coarse residual sweeps (sized
+// for the first coarse grid, plus a flag slot); per coarse grid l: 25 FP64
+// boxes (the 8 iterated fields in two copies, ln(1-phi), Fo, the old
+// pressures, k/mu_f, eta_phi, mu_s) and, above the coarsest grid, its FP32
+// residual (5 boxes).
+constexpr int MG_NB = 25;
+constexpr int MG_LP = 16, MG_FOX = 17, MG_PTO = 20, MG_PFO = 21, MG_KC = 22, MG_ETA = 23, MG_MUS = 24;
+
+int64_t box_of(const Geom& g) { return g.S * (int64_t)(g.nz + 1); }
+int64_t mg_stride(const Geom& g) { return box_of(g) + 32; }                       // doubles
+int64_t mg_res_doubles(const Geom& g) { return ((5 * (box_of(g) + 64) + 1) / 2 + 31) / 32 * 32; }
+
+Geom mg_coarse_geom(const Geom& f) {
+    Geom c = f;
+    c.nx = (f.nx + 1) / 2;
+    c.ny = (f.ny + 1) / 2;
+    c.nz = (f.nz + 1) / 2;
+    c.P = ((int64_t)c.nx + 1 + 31) / 32 * 32;
+    c.S = c.P * (int64_t)(c.ny + 1);
+    c.kz = KZ_MAX;
+    c.tall32 = 0;
+    return c;
+}
+
+bool mg_valid(const pt_mg_params* m) {
+    if (!m || m->version != PT_ABI_VERSION) return false;
+    if (m->levels != 0 && (m->levels < 2 || m->levels > PT_MG_MAX_LEVELS)) return false;
+    if (m->nu1 < 1 || m->nu2 < 0 || m->nu1 > 1000 || m->nu2 > 1000) return false;
+    if (m->coarse_sweeps < 1 || m->coarse_sweeps > 1000000 || m->n_pt < 1) return false;
+    if (!(m->c_v > 0.0 && std::isfinite(m->c_v)) || !(m->c_pf > 0.0 && std::isfinite(m->c_pf))) return false;
+    return true;
+}
+
+// Level geometries of a hierarchy; 0 levels if the grid cannot be coarsened.
+int mg_plan(const pt_grid* g, const pt_mg_params& m, Geom* out) {
+    out[0] = g->geom;
+    int L = 1;
+    while (L < PT_MG_MAX_LEVELS) {
+        const Geom& f = out[L - 1];
+        const int nmin = std::min(f.nx, std::min(f.ny, f.nz));
+        if (m.levels == 0 ? nmin <= 8 : L >= m.levels) break;
+        if (nmin < 4) break;                       // a coarse grid needs at least 2 cells per axis
+        out[L] = mg_coarse_geom(f);
+        ++L;
+    }
+    if (m.levels != 0 && L != m.levels) return 0;
+    return L >= 2 ? L : 0;
+}
+
+// Per-block maxima of the coarse grids' residual sweeps: the most blocks
+// of any coarse grid (the chunking can give a smaller grid more blocks).
+int64_t mg_part_blocks(const Geom* geo, int L) {
+    int64_t nb = 0;
+    for (int l = 1; l < L; ++l) nb = std::max(nb, norm_blocks(geo[l]));
+    return nb;
+}
+int64_t mg_part_doubles(const Geom* geo, int L) { return (mg_part_blocks(geo, L) * NNORM + NNORM + 1 + 31) / 32 * 32; }
+
+size_t mg_needed(const pt_grid* g, const pt_mg_params& m) {
+    Geom geo[PT_MG_MAX_LEVELS];
+    const int L = mg_plan(g, m, geo);
+    if (!L) return 0;
+    int64_t n = mg_res_doubles(geo[0]);
+    n += mg_part_doubles(geo, L);
+    for (int l = 1; l < L; ++l) {
+        n += MG_NB * mg_stride(geo[l]);
+        if (l < L - 1) n += mg_res_doubles(geo[l]);
+    }
+    return (size_t)n * sizeof(double);
+}
+
+// Workspace pieces.
+float* mg_res(pt_grid* g, int l, int q) {
+    double* base = g->gws;
+    if (l > 0) {
+        base += mg_res_doubles(g->mg_geom[0]) + mg_part_doubles(g->mg_geom, g->mg_levels);
+        for (int k = 1; k < l; ++k) base += MG_NB * mg_stride(g->mg_geom[k]) + mg_res_doubles(g->mg_geom[k]);
+        base += MG_NB * mg_stride(g->mg_geom[l]);
+    }
+    return reinterpret_cast<float*>(base) + (int64_t)q * (box_of(g->mg_geom[l]) + 64);
+}
+double* mg_partials(pt_grid* g) { return g->gws + mg_res_doubles(g->mg_geom[0]); }
+double* mg_box(pt_grid* g, int l, int b) {
+    double* base = g->gws + mg_res_doubles(g->mg_geom[0]) + mg_part_doubles(g->mg_geom, g->mg_levels);
+    for (int k = 1; k < l; ++k) base += MG_NB * mg_stride(g->mg_geom[k]) + mg_res_doubles(g->mg_geom[k]);
+    return base + (int64_t)b * mg_stride(g->mg_geom[l]);
+}
+
+// Sweep constants of grid l: the smoother's (or, for the coarsest grid, the
+// damped PT's) pseudo steps; on coarse grids no physical constant terms.
+Coef mg_coef(const pt_grid* g, int l, bool coarsest) {
+    const pt_params& p = g->prm;
+    const pt_mg_params& m = g->mgp;
+    const Geom& gl = g->mg_geom[l];
+    Coef c = g->coef;
+    const double dx = p.lx / gl.nx, dy = p.ly / gl.ny, dz = p.lz / gl.nz;
+    const double h = std::fmin(dx, std::fmin(dy, dz));
+    c.dxi = 1.0 / dx;
+    c.dyi = 1.0 / dy;
+    c.dzi = 1.0 / dz;
+    if (coarsest) {
+        const int nmax = std::max(gl.nx, std::max(gl.ny, gl.nz));
+        c.beta_n = p.beta_n;
+        c.dtauv_c = p.rho_i * h * h / (p.c_v * (1.0 + p.beta_n));
+        c.dtaupt_c = (1.0 + p.beta_n) / nmax;
+        c.dtaupf_c = h * h * (1.0 + p.beta_d * p.B / p.alpha) / p.c_pf;
+        c.dampx = 1.0 - p.damp_c / gl.nx;
+        c.dampy = 1.0 - p.damp_c / gl.ny;
+        c.dampz = 1.0 - p.damp_c / gl.nz;
+    } else {
+        c.beta_n = 0.0;
+        c.dtauv_c = p.rho_i * h * h / m.c_v;
+        c.dtaupt_c = 1.0 / m.n_pt;
+        c.dtaupf_c = h * h * (1.0 + p.beta_d * p.B / p.alpha) / m.c_pf;
+        c.dampx = c.dampy = c.dampz = 0.0;
+    }
+    if (l > 0) {
+        c.rhofg = c.rhosg = c.rhobg = c.buoy = 0.0;
+        c.gbg_half = 0.0;
+    }
+    return c;
+}
+
+SweepPtrs<double> mg_ptrs(pt_grid* g, int l) {
+    if (l == 0) {
+        SweepPtrs<double> p = sweep_ptrs(g);
+        p.res_fx = mg_res(g, 0, 0); p.res_fy = mg_res(g, 0, 1); p.res_fz = mg_res(g, 0, 2);
+        p.res_rpt = mg_res(g, 0, 3); p.res_rpf = mg_res(g, 0, 4);
+        return p;
+    }
+    SweepPtrs<double> p{};
+    const int src = g->mg_cur[l] ? 8 : 0, dst = g->mg_cur[l] ? 0 : 8;
+    p.vx = mg_box(g, l, src + 0); p.vy = mg_box(g, l, src + 1); p.vz = mg_box(g, l, src + 2);
+    p.pt = mg_box(g, l, src + 3); p.pf = mg_box(g, l, src + 4);
+    p.rx = mg_box(g, l, src + 5); p.ry = mg_box(g, l, src + 6); p.rz = mg_box(g, l, src + 7);
+    p.vx_o = mg_box(g, l, dst + 0); p.vy_o = mg_box(g, l, dst + 1); p.vz_o = mg_box(g, l, dst + 2);
+    p.pt_o = mg_box(g, l, dst + 3); p.pf_o = mg_box(g, l, dst + 4);
+    p.rx_o = mg_box(g, l, dst + 5); p.ry_o = mg_box(g, l, dst + 6); p.rz_o = mg_box(g, l, dst + 7);
+    p.lp = p.lpo = p.lp_o = mg_box(g, l, MG_LP);
+    p.fox = mg_box(g, l, MG_FOX); p.foy = mg_box(g, l, MG_FOX + 1); p.foz = mg_box(g, l, MG_FOX + 2);
+    p.pto = mg_box(g, l, MG_PTO); p.pfo = mg_box(g, l, MG_PFO);
+    p.kc = mg_box(g, l, MG_KC); p.eta = mg_box(g, l, MG_ETA); p.mus = mg_box(g, l, MG_MUS);
+    p.partials = mg_partials(g);
+    p.domain = mg_partials(g) + mg_part_blocks(g->mg_geom, g->mg_levels) * NNORM + NNORM;
+    if (l < g->mg_levels - 1) {
+        p.res_fx = mg_res(g, l, 0); p.res_fy = mg_res(g, l, 1); p.res_fz = mg_res(g, l, 2);
+        p.res_rpt = mg_res(g, l, 3); p.res_rpf = mg_res(g, l, 4);
+    }
+    return p;
+}
+
+// n linear sweeps on grid l with the smoother's (or the coarsest grid's) constants.
+pt_status mg_smooth(pt_grid* g, int l, int n) {
+    const bool coarsest = l == g->mg_levels - 1;
+    const Coef c = mg_coef(g, l, coarsest);
+    for (int k = 0; k < n; ++k) {
+        const SweepPtrs<double> p = mg_ptrs(g, l);
+        hipError_t e = launch_iteration(g->mg_geom[l], c, p, MD_LINEAR, 0, g->stream);
+        if (e != hipSuccess) return hip_fail(g, e, "multigrid sweep");
+        if (l == 0) {
+            for (int f = 0; f < PT_NPING; ++f)
+                if (f != PT_LP) g->cur[f] ^= 1;
+            g->iter += 1;
+        } else {
+            g->mg_cur[l] ^= 1;
+        }
+    }
+    return PT_OK;
+}
+
+// Residual of grid l into its FP32 boxes (grid 0: with the norms reduced).
+pt_status mg_residual(pt_grid* g, int l) {
+    const SweepPtrs<double> p = mg_ptrs(g, l);
+    const Coef c = l == 0 ? g->coef : mg_coef(g, l, false);
+    hipError_t e = launch_iteration(g->mg_geom[l], c, p, MD_RESID, 1, g->stream);
+    if (e != hipSuccess) return hip_fail(g, e, "multigrid residual");
+    return l == 0 ? reduce_norms(g) : PT_OK;
+}
+
+// Coarse-grid correction of grid l (its residual is in its FP32 boxes).
+pt_status mg_correct(pt_grid* g, int l) {
+    const int c = l + 1;
+    const Geom& gf = g->mg_geom[l];
+    const Geom& gc = g->mg_geom[c];
+    const int64_t nbox = box_of(gc);
+    hipError_t e = hipSuccess;
+    // the correction starts at zero (the present copies of V, Pt, Pf, R)
+    const int cp = g->mg_cur[c] ? 8 : 0;
+    for (int b = 0; b < 8 && e == hipSuccess; ++b) e = launch_fill(mg_box(g, c, cp + b), 0.0, nbox, g->stream);
+    // right-hand side: the restricted residual in the constant terms
+    for (int a = 0; a < 3 && e == hipSuccess; ++a)
+        e = launch_mg_restrict32(gf, gc, a + 1, mg_res(g, l, a), mg_box(g, c, MG_FOX + a), g->stream);
+    if (e == hipSuccess) {
+        const pt_params& p = g->prm;
+        // c(-pto + alpha pfo) = a, c(alpha pto - (alpha/B) pfo) = b, c = beta_d/dt
+        const double k = p.beta_d / p.dt, al = p.alpha, ab = p.alpha / p.B;
+        const double det = k * k * (ab - al * al);
+        const double m[4] = {-k * ab / det, -k * al / det, -k * al / det, -k / det};
+        e = launch_mg_restrict_fold(gf, gc, mg_res(g, l, 3), mg_res(g, l, 4), mg_box(g, c, MG_PTO),
+                                    mg_box(g, c, MG_PFO), m, g->stream);
+    }
+    if (e != hipSuccess) return hip_fail(g, e, "multigrid restriction");
+    pt_status st;
+    if (c == g->mg_levels - 1) {
+        st = mg_smooth(g, c, g->mgp.coarse_sweeps);
+    } else {
+        st = mg_smooth(g, c, g->mgp.nu1);
+        if (st == PT_OK) st = mg_residual(g, c);
+        if (st == PT_OK) st = mg_correct(g, c);
+        if (st == PT_OK) st = mg_smooth(g, c, g->mgp.nu2);
+    }
+    if (st != PT_OK) return st;
+    // add the interpolated correction to grid l's present copies
+    const int cc = g->mg_cur[c] ? 8 : 0;
+    for (int q = 0; q < 5 && e == hipSuccess; ++q) {
+        double* dst;
+        if (l == 0) {
+            const int fl[5] = {PT_VX, PT_VY, PT_VZ, PT_PT, PT_PF};
+            dst = cur(g, fl[q]);
+        } else {
+            dst = mg_box(g, l, (g->mg_cur[l] ? 8 : 0) + q);
+        }
+        e = launch_mg_prolong_add(gf, gc, q < 3 ? q + 1 : 0, mg_box(g, c, cc + q), dst, g->stream);
+    }
+    if (e != hipSuccess) return hip_fail(g, e, "multigrid prolongation");
+    return PT_OK;
+}
+
+// Coefficients of every coarse grid from its finer one.
+pt_status mg_coefficients(pt_grid* g) {
+    hipError_t e = hipSuccess;
+    for (int l = 1; l < g->mg_levels && e == hipSuccess; ++l) {
+        const Geom& gf = g->mg_geom[l - 1];
+        const Geom& gc = g->mg_geom[l];
+        const double* kc = l == 1 ? cur(g, PT_KC) : mg_box(g, l - 1, MG_KC);
+        const double* eta = l == 1 ? cur(g, PT_ETA) : mg_box(g, l - 1, MG_ETA);
+        const double* mus = l == 1 ? cur(g, PT_MUS) : mg_box(g, l - 1, MG_MUS);
+        const double* lp = l == 1 ? cur(g, PT_LP) : mg_box(g, l - 1, MG_LP);
+        e = launch_mg_restrict(gf, gc, 0, kc, mg_box(g, l, MG_KC), 1, g->stream);
+        if (e == hipSuccess) e = launch_mg_restrict(gf, gc, 0, eta, mg_box(g, l, MG_ETA), 0, g->stream);
+        if (e == hipSuccess) e = launch_mg_restrict(gf, gc, 0, mus, mg_box(g, l, MG_MUS), 0, g->stream);
+        if (e == hipSuccess) e = launch_mg_restrict(gf, gc, 0, lp, mg_box(g, l, MG_LP), 0, g->stream);
+    }
+    if (e != hipSuccess) return hip_fail(g, e, "multigrid coefficients");
+    return PT_OK;
+}
+
+pt_status mg_rho(pt_grid* g, double* r) {
+    pt_norms nm;
+    pt_status st = read_norms(g, &nm);
+    if (st != PT_OK) return st;
+    const double gv = nm.f, gp = std::fmax(nm.rpt, nm.rpf);
+    if (!g->ref_set) {
+        g->ref_v = gv;
+        g->ref_p = gp;
+        g->ref_set = true;
+    }
+    double v = 0.0;
+    if (g->ref_v > 0.0) v = std::fmax(v, gv / g->ref_v);
+    if (g->ref_p > 0.0) v = std::fmax(v, gp / g->ref_p);
+    *r = v;
+    return PT_OK;
+}
+
+pt_status solve_mg_core(pt_grid* g, double rtol, int64_t max_cycles, int64_t* cycles, double* rho) {
+    pt_status st = check_ready(g);
+    if (st != PT_OK) return st;
+    if (!g->gws) return fail(g, PT_EINVAL, "multigrid workspace not bound");
+    if (!(g->prm.beta_d > 0.0) || g->prm.alpha * g->prm.alpha * g->prm.B == g->prm.alpha)
+        return fail(g, PT_EINVAL, "multigrid needs beta_d > 0 and alpha B != 1 (the pressure terms carry the "
+                                  "coarse right-hand side)");
+    st = mg_coefficients(g);
+    if (st != PT_OK) return st;
+    double r = INFINITY;
+    if (!g->ref_set) {
+        // the reference is the residual of the state the solve starts from
+        st = mg_residual(g, 0);
+        if (st == PT_OK) st = mg_rho(g, &r);
+        if (st != PT_OK) return st;
+    }
+    int64_t c = 0;
+    for (;;) {
+        st = mg_smooth(g, 0, g->mgp.nu1);
+        if (st == PT_OK) st = mg_residual(g, 0);
+        if (st == PT_OK) st = mg_rho(g, &r);
+        if (st != PT_OK) break;
+        if (r <= rtol || c >= max_cycles) break;
+        st = mg_correct(g, 0);
+        if (st == PT_OK) st = mg_smooth(g, 0, g->mgp.nu2);
+        if (st != PT_OK) break;
+        ++c;
+    }
+    if (cycles) *cycles = c;
+    if (rho) *rho = r;
+    if (st != PT_OK) return st;
+    return (r <= rtol) ? PT_OK : PT_ENOTCONV;
+}
+
+}  // namespace
+
+extern "C" {
+
+pt_status pt_mg_workspace_size(const pt_grid* g, const pt_mg_params* mg, size_t* bytes) {
+    if (!g || !bytes || !mg_valid(mg)) return PT_EINVAL;
+    const size_t n = mg_needed(g, *mg);
+    if (!n) return PT_EINVAL;
+    *bytes = n;
+    return PT_OK;
+}
+
+pt_status pt_bind_mg_workspace(pt_grid* g, const pt_mg_params* mg, void* dev_ptr, size_t bytes) {
+    if (!g) return PT_EINVAL;
+    if (!mg_valid(mg)) return fail(g, PT_EINVAL, "bad multigrid parameters");
+    const size_t need = mg_needed(g, *mg);
+    if (!need) return fail(g, PT_EINVAL, "grid too small to coarsen to the requested levels");
+    if (!dev_ptr || (reinterpret_cast<uintptr_t>(dev_ptr) & 255u) || bytes < need)
+        return fail(g, PT_EINVAL, "multigrid workspace missing, unaligned or too small");
+    g->mgp = *mg;
+    g->mg_levels = mg_plan(g, *mg, g->mg_geom);
+    g->gws = static_cast<double*>(dev_ptr);
+    g->gws_bytes = bytes;
+    for (int l = 0; l < PT_MG_MAX_LEVELS; ++l) g->mg_cur[l] = 0;
+    // the walls' normal faces of the coarse corrections are never written:
+    // clear the whole workspace once
+    hipError_t e = launch_fill(g->gws, 0.0, (int64_t)(need / sizeof(double)), g->stream);
+    if (e != hipSuccess) return hip_fail(g, e, "multigrid workspace clear");
+    return PT_OK;
+}
+
+pt_status pt_mg_levels(const pt_grid* g, int32_t* levels, int32_t* counts) {
+    if (!g || !levels) return PT_EINVAL;
+    *levels = g->gws ? g->mg_levels : 0;
+    if (counts)
+        for (int l = 0; l < *levels; ++l) {
+            counts[3 * l] = g->mg_geom[l].nx;
+            counts[3 * l + 1] = g->mg_geom[l].ny;
+            counts[3 * l + 2] = g->mg_geom[l].nz;
+        }
+    return PT_OK;
+}
+
+pt_status pt_solve_mg(pt_grid* g, double rtol, int64_t max_cycles, int64_t* cycles, double* rho) {
+    if (!g || !(rtol > 0.0) || max_cycles < 0) return PT_EINVAL;
+    return solve_mg_core(g, rtol, max_cycles, cycles, rho);
+}
 
 pt_status pt_picard_step(pt_grid* g, int32_t update_history, int32_t n_picard, double rtol, int64_t max_iter,
                          int32_t mixed, double eta_in, int64_t* sweeps, double* rho) {
     if (!g || n_picard < 1 || !(rtol > 0.0) || max_iter < 1) return PT_EINVAL;
-    if (mixed && !(eta_in > 0.0 && eta_in < 1.0)) return PT_EINVAL;
+    if (mixed < PT_SOLVER_FP64 || mixed > PT_SOLVER_MG) return PT_EINVAL;
+    if (mixed == PT_SOLVER_MIXED && !(eta_in > 0.0 && eta_in < 1.0)) return PT_EINVAL;
+    if (mixed == PT_SOLVER_MG && !g->gws) return fail(g, PT_EINVAL, "multigrid workspace not bound");
     pt_status st = pt_begin_step(g, update_history ? 1 : 0);
     if (st != PT_OK) return st;
     int64_t total = 0;
@@ -1152,7 +1524,9 @@ pt_status pt_picard_step(pt_grid* g, int32_t update_history, int32_t n_picard, d
         if (st != PT_OK) return st;
         int64_t it = 0;
         double r = 0.0;
-        if (mixed) {
+        if (mixed == PT_SOLVER_MG) {
+            st = pt_solve_mg(g, rtol, max_iter, &it, &r);
+        } else if (mixed == PT_SOLVER_MIXED) {
             int32_t outer = 0;
             st = pt_solve_mixed(g, rtol, eta_in, max_iter, PICARD_MAX_CORRECTIONS, &it, &outer, &r);
         } else {

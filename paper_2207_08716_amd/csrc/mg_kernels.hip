@@ -1,0 +1,217 @@
+// Grid transfers of the geometric multigrid solver for the linear Picard
+// stage (the thesis's outlook: geometric multigrid with weighted-Jacobi
+// smoothing, which the PT iteration becomes without damping).
+//
+// A coarse grid has ceil(n/2) cells per axis on the same domain, so grids
+// with odd counts (511 -> 256 -> 128 ...) are not nested.  Transfers are
+// tensor products of one-dimensional linear interpolation between the two
+// grids' point positions, per staggering: cell centres (i + 1/2) h, taken
+// constant beyond the outermost coarse centres, and faces i h, which both
+// grids have at the walls.  Prolongation P interpolates a coarse correction
+// to the fine points; restriction is P's transpose with every row
+// normalised to weight sum 1 (an average of the fine values around a coarse
+// point).  Normal faces on the walls carry no equation: the restriction
+// skips them and gives zero there, the prolongation leaves them alone.
+#include "pt_internal.h"
+
+namespace ptk {
+namespace {
+
+constexpr int TB = 256;
+
+// Fine index i of an axis with nf fine and nc coarse cells, in coarse
+// units: the coarse index j0 and the weight t of j0 + 1 (1 - t of j0).
+__device__ __forceinline__ void pw(int i, int nf, int nc, bool face, int& j0, double& t) {
+    if (face) {
+        const double u = (double)i * nc / nf;
+        j0 = min((int)floor(u), nc - 1);
+        t = u - j0;
+    } else {
+        const double u = ((double)i + 0.5) * nc / nf - 0.5;
+        if (u <= 0.0) {
+            j0 = 0;
+            t = 0.0;
+        } else if (u >= (double)(nc - 1)) {
+            j0 = nc - 1;
+            t = 0.0;
+        } else {
+            j0 = (int)floor(u);
+            t = u - j0;
+        }
+    }
+}
+
+// P's entry (fine i, coarse J) of one axis.
+__device__ __forceinline__ double pweight(int i, int J, int nf, int nc, bool face) {
+    int j0;
+    double t;
+    pw(i, nf, nc, face, j0, t);
+    return J == j0 ? 1.0 - t : (J == j0 + 1 ? t : 0.0);
+}
+
+// Fine indices whose interpolation can involve coarse index J.
+__device__ __forceinline__ void prange(int J, int nf, int nc, bool face, int& lo, int& hi) {
+    const double r = (double)nf / nc;
+    if (face) {
+        lo = max(0, (int)floor((J - 1) * r));
+        hi = min(nf, (int)ceil((J + 1) * r));
+    } else {
+        lo = max(0, (int)floor((J - 0.5) * r - 0.5));
+        hi = min(nf - 1, (int)ceil((J + 1.5) * r - 0.5));
+    }
+}
+
+struct Ext {
+    int nx, ny, nz;     // cells of the grid
+    int64_t P, S;       // row and plane pitch
+};
+__host__ __device__ inline Ext ext(const Geom& g) { return Ext{g.nx, g.ny, g.nz, g.P, g.S}; }
+
+// Restriction of one field of staggering (fx, fy, fz: face along that
+// axis).  mode 0: average, 1: harmonic average.  Walls' normal faces: 0.
+template <typename TS>
+__global__ __launch_bounds__(TB) void k_mg_restrict(Ext f, Ext c, bool fx, bool fy, bool fz, const TS* __restrict__ src,
+                                                    double* __restrict__ dst, int mode) {
+    const int ex = c.nx + fx, ey = c.ny + fy, ez = c.nz + fz;
+    const int64_t n = (int64_t)ex * ey * ez;
+    for (int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x; t < n; t += (int64_t)gridDim.x * TB) {
+        const int I = (int)(t % ex), J = (int)((t / ex) % ey), K = (int)(t / ((int64_t)ex * ey));
+        const int64_t o = (int64_t)K * c.S + (int64_t)J * c.P + I;
+        if ((fx && (I == 0 || I == c.nx)) || (fy && (J == 0 || J == c.ny)) || (fz && (K == 0 || K == c.nz))) {
+            dst[o] = 0.0;
+            continue;
+        }
+        int xl, xh, yl, yh, zl, zh;
+        prange(I, f.nx, c.nx, fx, xl, xh);
+        prange(J, f.ny, c.ny, fy, yl, yh);
+        prange(K, f.nz, c.nz, fz, zl, zh);
+        // the walls' normal faces are not equations
+        if (fx) { xl = max(xl, 1); xh = min(xh, f.nx - 1); }
+        if (fy) { yl = max(yl, 1); yh = min(yh, f.ny - 1); }
+        if (fz) { zl = max(zl, 1); zh = min(zh, f.nz - 1); }
+        double s = 0.0, ws = 0.0;
+        for (int k = zl; k <= zh; ++k) {
+            const double wz = pweight(k, K, f.nz, c.nz, fz);
+            if (wz == 0.0) continue;
+            for (int j = yl; j <= yh; ++j) {
+                const double wy = pweight(j, J, f.ny, c.ny, fy) * wz;
+                if (wy == 0.0) continue;
+                const TS* row = src + (int64_t)k * f.S + (int64_t)j * f.P;
+                for (int i = xl; i <= xh; ++i) {
+                    const double w = pweight(i, I, f.nx, c.nx, fx) * wy;
+                    if (w == 0.0) continue;
+                    const double v = (double)row[i];
+                    s += w * (mode ? 1.0 / v : v);
+                    ws += w;
+                }
+            }
+        }
+        dst[o] = (ws > 0.0) ? (mode ? ws / s : s / ws) : 0.0;
+    }
+}
+
+// Restricted pressure residuals (a, b) folded into old-pressure fields:
+// pto = m00 a + m01 b, pfo = m10 a + m11 b, the values whose terms in
+// r_Pt and r_Pf at the zero state are a and b.
+__global__ __launch_bounds__(TB) void k_mg_restrict_fold(Ext f, Ext c, const float* __restrict__ rpt,
+                                                         const float* __restrict__ rpf, double* __restrict__ pto,
+                                                         double* __restrict__ pfo, double m00, double m01,
+                                                         double m10, double m11) {
+    const int64_t n = (int64_t)c.nx * c.ny * c.nz;
+    for (int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x; t < n; t += (int64_t)gridDim.x * TB) {
+        const int I = (int)(t % c.nx), J = (int)((t / c.nx) % c.ny), K = (int)(t / ((int64_t)c.nx * c.ny));
+        int xl, xh, yl, yh, zl, zh;
+        prange(I, f.nx, c.nx, false, xl, xh);
+        prange(J, f.ny, c.ny, false, yl, yh);
+        prange(K, f.nz, c.nz, false, zl, zh);
+        double a = 0.0, b = 0.0, ws = 0.0;
+        for (int k = zl; k <= zh; ++k) {
+            const double wz = pweight(k, K, f.nz, c.nz, false);
+            if (wz == 0.0) continue;
+            for (int j = yl; j <= yh; ++j) {
+                const double wy = pweight(j, J, f.ny, c.ny, false) * wz;
+                if (wy == 0.0) continue;
+                const int64_t row = (int64_t)k * f.S + (int64_t)j * f.P;
+                for (int i = xl; i <= xh; ++i) {
+                    const double w = pweight(i, I, f.nx, c.nx, false) * wy;
+                    if (w == 0.0) continue;
+                    a += w * (double)rpt[row + i];
+                    b += w * (double)rpf[row + i];
+                    ws += w;
+                }
+            }
+        }
+        a /= ws;
+        b /= ws;
+        const int64_t o = (int64_t)K * c.S + (int64_t)J * c.P + I;
+        pto[o] = m00 * a + m01 * b;
+        pfo[o] = m10 * a + m11 * b;
+    }
+}
+
+// fine += P coarse for one field of staggering (fx, fy, fz); the walls'
+// normal faces keep their values.
+__global__ __launch_bounds__(TB) void k_mg_prolong_add(Ext f, Ext c, bool fx, bool fy, bool fz,
+                                                       const double* __restrict__ src, double* __restrict__ dst) {
+    const int ex = f.nx + fx, ey = f.ny + fy, ez = f.nz + fz;
+    const int64_t n = (int64_t)ex * ey * ez;
+    for (int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x; t < n; t += (int64_t)gridDim.x * TB) {
+        const int i = (int)(t % ex), j = (int)((t / ex) % ey), k = (int)(t / ((int64_t)ex * ey));
+        if ((fx && (i == 0 || i == f.nx)) || (fy && (j == 0 || j == f.ny)) || (fz && (k == 0 || k == f.nz))) continue;
+        int x0, y0, z0;
+        double tx, ty, tz;
+        pw(i, f.nx, c.nx, fx, x0, tx);
+        pw(j, f.ny, c.ny, fy, y0, ty);
+        pw(k, f.nz, c.nz, fz, z0, tz);
+        // the second point of an axis: inside the coarse extent (its weight
+        // is zero where the first point is the last one)
+        const int x1 = min(x0 + 1, c.nx - 1 + fx), y1 = min(y0 + 1, c.ny - 1 + fy), z1 = min(z0 + 1, c.nz - 1 + fz);
+        auto at = [&](int a, int b, int d) { return src[(int64_t)d * c.S + (int64_t)b * c.P + a]; };
+        const double v0 = (1.0 - tx) * at(x0, y0, z0) + tx * at(x1, y0, z0);
+        const double v1 = (1.0 - tx) * at(x0, y1, z0) + tx * at(x1, y1, z0);
+        const double v2 = (1.0 - tx) * at(x0, y0, z1) + tx * at(x1, y0, z1);
+        const double v3 = (1.0 - tx) * at(x0, y1, z1) + tx * at(x1, y1, z1);
+        const double v = (1.0 - tz) * ((1.0 - ty) * v0 + ty * v1) + tz * ((1.0 - ty) * v2 + ty * v3);
+        dst[(int64_t)k * f.S + (int64_t)j * f.P + i] += v;
+    }
+}
+
+unsigned blocks_for(int64_t n) { return (unsigned)std::min<int64_t>((n + TB - 1) / TB, 65536); }
+
+}  // namespace
+
+hipError_t launch_mg_restrict(const Geom& gf, const Geom& gc, int kind, const double* src, double* dst, int harmonic,
+                              hipStream_t s) {
+    const bool fx = kind == 1, fy = kind == 2, fz = kind == 3;
+    const int64_t n = (int64_t)(gc.nx + fx) * (gc.ny + fy) * (gc.nz + fz);
+    hipLaunchKernelGGL(k_mg_restrict<double>, dim3(blocks_for(n)), dim3(TB), 0, s, ext(gf), ext(gc), fx, fy, fz, src,
+                       dst, harmonic);
+    return hipGetLastError();
+}
+
+hipError_t launch_mg_restrict32(const Geom& gf, const Geom& gc, int kind, const float* src, double* dst,
+                                hipStream_t s) {
+    const bool fx = kind == 1, fy = kind == 2, fz = kind == 3;
+    const int64_t n = (int64_t)(gc.nx + fx) * (gc.ny + fy) * (gc.nz + fz);
+    hipLaunchKernelGGL(k_mg_restrict<float>, dim3(blocks_for(n)), dim3(TB), 0, s, ext(gf), ext(gc), fx, fy, fz, src,
+                       dst, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_mg_restrict_fold(const Geom& gf, const Geom& gc, const float* rpt, const float* rpf, double* pto,
+                                   double* pfo, const double m[4], hipStream_t s) {
+    const int64_t n = (int64_t)gc.nx * gc.ny * gc.nz;
+    hipLaunchKernelGGL(k_mg_restrict_fold, dim3(blocks_for(n)), dim3(TB), 0, s, ext(gf), ext(gc), rpt, rpf, pto, pfo,
+                       m[0], m[1], m[2], m[3]);
+    return hipGetLastError();
+}
+
+hipError_t launch_mg_prolong_add(const Geom& gf, const Geom& gc, int kind, const double* src, double* dst,
+                                 hipStream_t s) {
+    const bool fx = kind == 1, fy = kind == 2, fz = kind == 3;
+    const int64_t n = (int64_t)(gf.nx + fx) * (gf.ny + fy) * (gf.nz + fz);
+    hipLaunchKernelGGL(k_mg_prolong_add, dim3(blocks_for(n)), dim3(TB), 0, s, ext(gf), ext(gc), fx, fy, fz, src, dst);
+    return hipGetLastError();
+}
+
+}  // namespace ptk

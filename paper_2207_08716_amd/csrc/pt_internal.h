@@ -245,6 +245,21 @@ hipError_t launch_adjoint_gradient(const Geom& g, const Coef& c, const double* k
 hipError_t launch_exp_cells(const Geom& g, const double* src, double* dst, hipStream_t s);
 hipError_t launch_apply_correction(const Geom& g, const MixedPtrs& m, hipStream_t s);
 
+// Multigrid transfers between a fine grid gf and its coarse grid gc
+// (mg_kernels.hip).  kind: 0 cells, 1/2/3 faces normal to x/y/z.
+// Restriction: averages (harmonic != 0: harmonic averages) of the fine
+// values around each coarse point, zero on the walls' normal faces.
+hipError_t launch_mg_restrict(const Geom& gf, const Geom& gc, int kind, const double* src, double* dst, int harmonic,
+                              hipStream_t s);
+hipError_t launch_mg_restrict32(const Geom& gf, const Geom& gc, int kind, const float* src, double* dst,
+                                hipStream_t s);
+// Restricted r_Pt, r_Pf (a, b) -> pto = m[0] a + m[1] b, pfo = m[2] a + m[3] b.
+hipError_t launch_mg_restrict_fold(const Geom& gf, const Geom& gc, const float* rpt, const float* rpf, double* pto,
+                                   double* pfo, const double m[4], hipStream_t s);
+// dst (fine) += interpolated src (coarse); the walls' normal faces are kept.
+hipError_t launch_mg_prolong_add(const Geom& gf, const Geom& gc, int kind, const double* src, double* dst,
+                                 hipStream_t s);
+
 // Adjoint of a Picard run (adjoint_kernels.hip).  rhs holds -xbar, the
 // right-hand side of the transposed stage solve in the slots of the
 // correction sweep (momentum rows on the faces, r_Pt and r_Pf in the cells).

@@ -115,6 +115,10 @@ class Grid:
             _check(self.lib, h, self.lib.pt_bind_adjoint_workspace(h, C.c_void_p(self.aws.data_ptr()),
                                                                    self.aws_bytes, int(self.aws_sensors)),
                    "bind adjoint")
+        if getattr(self, "gws", None) is not None:
+            _check(self.lib, h, self.lib.pt_bind_mg_workspace(h, C.byref(self.gws_params),
+                                                              C.c_void_p(self.gws.data_ptr()),
+                                                              self.gws.numel() * 8), "bind mg")
 
     # ---- resuming on a new handle ----------------------------------------------
     def counters(self) -> abi.Counters:
@@ -238,18 +242,60 @@ class Grid:
     def porosity_step(self):
         _check(self.lib, self.h, self.lib.pt_porosity_step(self.h), "porosity_step")
 
-    def picard_step(self, update_history, n_picard, rtol, max_iter=2_000_000, mixed=False, eta_in=1e-4):
+    def picard_step(self, update_history, n_picard, rtol, max_iter=2_000_000, mixed=False, eta_in=1e-4,
+                    solver=None):
         """One physical step of the Picard schedule (see pt_picard_step):
-        returns (sweeps, rho, converged)."""
-        if mixed:
+        returns (sweeps, rho, converged).  solver: "fp64", "mixed" or "mg"
+        (default: "mixed" if mixed else "fp64"); for "mg", max_iter bounds
+        the V-cycles of a stage and sweeps counts V-cycles."""
+        solver = solver or ("mixed" if mixed else "fp64")
+        code = {"fp64": abi.SOLVER_FP64, "mixed": abi.SOLVER_MIXED, "mg": abi.SOLVER_MG}[solver]
+        if solver == "mixed":
             self.enable_mixed()
+        elif solver == "mg":
+            self.enable_mg()
         sweeps = C.c_int64()
         rho = C.c_double()
         st = _check(self.lib, self.h, self.lib.pt_picard_step(self.h, int(bool(update_history)), int(n_picard),
-                                                               float(rtol), int(max_iter), int(bool(mixed)),
+                                                               float(rtol), int(max_iter), code,
                                                                float(eta_in), C.byref(sweeps), C.byref(rho)),
                     "picard_step")
         return sweeps.value, rho.value, st == 0
+
+    # ---- geometric multigrid ------------------------------------------------
+    def enable_mg(self, **params):
+        """Allocate and bind the multigrid workspace (see pt_mg_params; keyword
+        arguments override its defaults).  Rebinds when the parameters change."""
+        mp = abi.mg_params(**params)
+        key = tuple(getattr(mp, n) for n, _ in abi.MgParams._fields_)
+        if getattr(self, "gws", None) is not None and self.gws_key == key:
+            return
+        nbytes = C.c_size_t()
+        _check(self.lib, self.h, self.lib.pt_mg_workspace_size(self.h, C.byref(mp), C.byref(nbytes)), "mg size")
+        self.gws = None
+        with torch.cuda.stream(self.stream):
+            self.gws = torch.empty((nbytes.value + 7) // 8, dtype=torch.float64, device=self.device)
+        _check(self.lib, self.h, self.lib.pt_bind_mg_workspace(self.h, C.byref(mp), C.c_void_p(self.gws.data_ptr()),
+                                                               nbytes.value), "bind mg")
+        self.gws_key = key
+        self.gws_params = mp
+
+    def mg_levels(self):
+        """Cell counts (nx, ny, nz) of every grid of the bound hierarchy."""
+        n = C.c_int32()
+        counts = (C.c_int32 * (3 * abi.MG_MAX_LEVELS))()
+        _check(self.lib, self.h, self.lib.pt_mg_levels(self.h, C.byref(n), counts), "mg levels")
+        return [tuple(counts[3 * l:3 * l + 3]) for l in range(n.value)]
+
+    def solve_mg(self, rtol, max_cycles=200, **params):
+        """Multigrid solve of the present Picard stage (see pt_solve_mg):
+        returns (cycles, rho, converged)."""
+        self.enable_mg(**params)
+        cyc = C.c_int64()
+        rho = C.c_double()
+        st = _check(self.lib, self.h, self.lib.pt_solve_mg(self.h, float(rtol), int(max_cycles), C.byref(cyc),
+                                                            C.byref(rho)), "solve_mg")
+        return cyc.value, rho.value, st == 0
 
     # ---- mixed precision ----------------------------------------------------
     def enable_mixed(self):

@@ -152,6 +152,45 @@ def test_driver_and_adjoint_entry_points_validate_on_the_host(lib):
         lib.pt_destroy(h)
 
 
+def test_multigrid_entry_points_validate_on_the_host(lib):
+    p = abi.params_from(inputs.Physics(), False)
+    h = C.c_void_p()
+    assert lib.pt_create(63, 40, 17, 64, C.byref(p), C.byref(h)) == 0
+    try:
+        sz = C.c_size_t()
+        good = abi.mg_params()
+        assert lib.pt_mg_workspace_size(h, C.byref(good), C.byref(sz)) == 0 and sz.value > 0
+        # 63 x 40 x 17 -> 32 x 20 x 9 -> 16 x 10 x 5: the automatic hierarchy
+        # stops at the first grid with an axis of at most 8 cells
+        three = abi.mg_params(levels=3)
+        sz3 = C.c_size_t()
+        assert lib.pt_mg_workspace_size(h, C.byref(three), C.byref(sz3)) == 0 and sz3.value == sz.value
+        # a fourth grid (8 x 5 x 3) is allowed on request; a fifth would halve
+        # an axis of 3 cells
+        assert lib.pt_mg_workspace_size(h, C.byref(abi.mg_params(levels=4)), C.byref(sz)) == 0
+        assert lib.pt_mg_workspace_size(h, C.byref(abi.mg_params(levels=5)), C.byref(sz)) == -1
+        for bad in (dict(levels=1), dict(levels=13), dict(nu1=0), dict(nu2=-1), dict(coarse_sweeps=0),
+                    dict(n_pt=0), dict(c_v=0.0), dict(c_pf=float("nan"))):
+            q = abi.mg_params(**bad)
+            assert lib.pt_mg_workspace_size(h, C.byref(q), C.byref(sz)) == -1, bad
+        q = abi.mg_params()
+        q.version = 1
+        assert lib.pt_mg_workspace_size(h, C.byref(q), C.byref(sz)) == -1
+        assert lib.pt_bind_mg_workspace(h, C.byref(good), C.c_void_p(0x1008), 1 << 40) == -1
+        assert lib.pt_bind_mg_workspace(h, C.byref(good), C.c_void_p(0x1000), 8) == -1
+        n = C.c_int32()
+        assert lib.pt_mg_levels(h, C.byref(n), None) == 0 and n.value == 0
+        cyc, rho = C.c_int64(), C.c_double()
+        assert lib.pt_solve_mg(h, 0.0, 10, C.byref(cyc), C.byref(rho)) == -1
+        assert lib.pt_solve_mg(h, 1e-8, -1, C.byref(cyc), C.byref(rho)) == -1
+        assert lib.pt_solve_mg(h, 1e-8, 10, C.byref(cyc), C.byref(rho)) == -1      # nothing bound
+        assert lib.pt_picard_step(h, 0, 2, 1e-8, 100, abi.SOLVER_MG, 0.0, C.byref(cyc), C.byref(rho)) == -1
+        assert b"multigrid" in lib.pt_last_error(h)
+        assert lib.pt_picard_step(h, 0, 2, 1e-8, 100, 3, 0.0, C.byref(cyc), C.byref(rho)) == -1
+    finally:
+        lib.pt_destroy(h)
+
+
 def test_counters_round_trip_on_the_host(lib):
     """pt_get_counters / pt_set_counters carry the host-side state of a handle
     to another one (no device call)."""

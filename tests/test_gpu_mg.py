@@ -1,0 +1,124 @@
+"""Geometric multigrid for the linear Picard stage (the thesis's outlook)
+through the C ABI.  Multigrid changes how the stage system is solved, not
+the system: its converged state is the oracle's converged linear solve (the
+plain definition of the stage), to the solve tolerance.
+
+* stage solves on even, odd (non-nested coarse grids) and ragged grids,
+  with the cap, lognormal k0 and a history term: every field against the
+  oracle's stage solved to 1e-12, and against the library's own PT solve;
+* a whole Picard step (5 stages, porosity steps between them) with the
+  multigrid stage solver against the oracle's Picard step;
+* the hierarchy the library builds, and V-cycle counts that stay flat as
+  the grid is refined (the property multigrid is for).
+"""
+import dataclasses
+import time
+
+import numpy as np
+import pytest
+
+from paper_2207_08716_amd import inputs
+
+from test_gpu_parity import _pair, _rel
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("vx", "vy", "vz", "pt", "pf")
+
+
+def _stage_pair(cfg, steps=1):
+    """GPU grid and oracle with `steps` Picard steps done (so that the second
+    has a stress history), then a begin_step and one refresh: a stage system
+    defined on both sides."""
+    g, o = _pair(cfg)
+    for s in range(steps - 1):
+        g.picard_step(s >= 1, 2, 1e-9)
+        o.begin_step()
+        for _ in range(2):
+            o.refresh(1.0, 1.0)
+            o.solve_linear(1e-9, 2_000_000)
+            o.porosity_step()
+        o.end_step()
+    g.begin_step(steps >= 2)
+    o.begin_step()
+    g.refresh(1.0, 1.0)
+    o.refresh(1.0, 1.0)
+    return g, o
+
+
+@pytest.mark.parametrize("shape,steps", [((32, 32, 32), 1), ((33, 33, 33), 1), ((40, 30, 22), 2)])
+def test_mg_stage_solve_matches_the_oracle_stage(shape, steps):
+    nx, ny, nz = shape
+    cfg = dataclasses.replace(inputs.config_mixed(nx), nx=nx, ny=ny, nz=nz)
+    g, o = _stage_pair(cfg, steps)
+    it_o, rho_o = o.solve_linear(1e-12, 4_000_000)
+    assert rho_o <= 1e-12
+    t0 = time.time()
+    cycles, rho, ok = g.solve_mg(1e-11, max_cycles=200)
+    print(f"{shape}: levels {g.mg_levels()} cycles {cycles} rho {rho:.2e} ({time.time() - t0:.2f} s); "
+          f"oracle PT {it_o} iterations", flush=True)
+    assert ok and cycles <= 60
+    worst = {k: _rel(g.get(k), o.f[k]) for k in FIELDS}
+    print(worst, flush=True)
+    assert max(worst.values()) <= 1e-8, worst
+
+
+def test_mg_and_pt_reach_the_same_stage_solution():
+    cfg = inputs.config_mixed(48)
+    f = inputs.initial_fields(cfg)
+    from paper_2207_08716_amd import schedules
+    out = {}
+    for solver in ("pt", "mg"):
+        g = schedules.make_grid(cfg, f)
+        g.begin_step(False)
+        g.refresh(1.0, 1.0)
+        if solver == "pt":
+            it, rho, ok = g.solve_linear(1e-11, 4_000_000)
+        else:
+            it, rho, ok = g.solve_mg(1e-11)
+        assert ok
+        out[solver] = {k: g.get(k) for k in FIELDS}
+        print(solver, it, rho, flush=True)
+    worst = {k: _rel(out["mg"][k], out["pt"][k]) for k in FIELDS}
+    print(worst, flush=True)
+    assert max(worst.values()) <= 1e-8, worst
+
+
+def test_mg_picard_step_matches_the_oracle_step():
+    n, rtol = 24, 1e-10
+    cfg = inputs.config_fp64_picard(n)
+    g, o = _pair(cfg)
+    cycles, rho, ok = g.picard_step(False, 5, rtol, max_iter=200, solver="mg")
+    assert ok and rho <= rtol
+    o.begin_step()
+    for _ in range(5):
+        o.refresh(1.0, 1.0)
+        it_o, rho_o = o.solve_linear(1e-12, 4_000_000)
+        assert rho_o <= 1e-12
+        o.porosity_step()
+    print(f"multigrid Picard step: {cycles} V-cycles, rho {rho:.2e}", flush=True)
+    worst = {k: _rel(g.get(k), o.f[k]) for k in FIELDS + ("lp",)}
+    print(worst, flush=True)
+    assert max(worst.values()) <= 1e-7, worst
+
+
+def test_mg_hierarchy_and_cycle_counts_flat_under_refinement():
+    from paper_2207_08716_amd import schedules
+    counts = {}
+    for n in (31, 63, 127):
+        cfg = inputs.config_mixed(n)
+        g = schedules.make_grid(cfg, inputs.initial_fields(cfg))
+        g.begin_step(False)
+        g.refresh(1.0, 1.0)
+        cycles, rho, ok = g.solve_mg(1e-8)
+        lv = g.mg_levels()
+        assert lv[0] == (n, n, n)
+        for a, b in zip(lv, lv[1:]):
+            assert b == tuple((v + 1) // 2 for v in a)
+        assert min(lv[-1]) <= 8 < min(lv[-2])
+        assert ok
+        counts[n] = cycles
+        g.close()
+    print(counts, flush=True)
+    # PT needs ~n^2 sweeps here; the V-cycle count stays bounded
+    assert counts[127] <= counts[31] + 8, counts
