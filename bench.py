@@ -116,12 +116,12 @@ def cpu_baseline(cfg, fields, ctx_n=255, single_n=64):
     }
 
 
-def time_to_tol(n: int, rtol: float = 1e-8, n_picard: int = 5, eta_in: float = 1e-4, modes=("fp64", "mixed")):
+def time_to_tol(n: int, rtol: float = 1e-8, n_picard: int = 5, eta_in: float = 1e-4, modes=("fp64", "mixed", "mg")):
     """Wall time of one physical step of the Picard schedule (n_picard stages,
     each linear solve to a relative residual rtol) on the mixed workload at n^3:
-    FP64 PT sweeps against FP32 sweeps inside FP64 defect correction, on the
-    same GPU, from the same initial state (n_picard = 1: the step's first
-    stage alone; modes: either or both)."""
+    FP64 PT sweeps, FP32 sweeps inside FP64 defect correction, and FP64
+    multigrid V-cycles, on the same GPU, from the same initial state
+    (n_picard = 1: the step's first stage alone; modes: any of the three)."""
     import numpy as np
     import torch
     from paper_2207_08716_amd import inputs, schedules
@@ -136,6 +136,7 @@ def time_to_tol(n: int, rtol: float = 1e-8, n_picard: int = 5, eta_in: float = 1
     w.refresh(1.0, 1.0)
     w.solve_linear(1e-2, 1000)
     w.solve_mixed(1e-2, 1e-1, 1000, 2)
+    w.solve_mg(1e-2, 5)
     w.porosity_step()
     torch.cuda.synchronize()
     del w
@@ -149,6 +150,9 @@ def time_to_tol(n: int, rtol: float = 1e-8, n_picard: int = 5, eta_in: float = 1
         g = schedules.make_grid(cfg, f)
         if mode == "mixed":
             g.enable_mixed()
+        elif mode == "mg":
+            g.enable_mg()
+            out["mg_levels"] = g.mg_levels()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         g.begin_step(False)
@@ -165,6 +169,14 @@ def time_to_tol(n: int, rtol: float = 1e-8, n_picard: int = 5, eta_in: float = 1
                     it, rho, ok = g.solve_linear(rtol, chunk)
                     total += it
                     print(f"time-to-tol fp64 n={n} stage {len(its) + 1}: {total} iterations rho={rho:.2e}",
+                          file=sys.stderr, flush=True)
+                its.append(total)
+            elif mode == "mg":
+                total, ok = 0, False
+                while not ok and total < 2000:
+                    cyc, rho, ok = g.solve_mg(rtol, 10)
+                    total += cyc
+                    print(f"time-to-tol mg n={n} stage {len(its) + 1}: {total} V-cycles rho={rho:.2e}",
                           file=sys.stderr, flush=True)
                 its.append(total)
             else:
@@ -188,13 +200,16 @@ def time_to_tol(n: int, rtol: float = 1e-8, n_picard: int = 5, eta_in: float = 1
         g.close()
         del g
         torch.cuda.empty_cache()
-    if "fp64" in fields and "mixed" in fields:
-        out["speedup_mixed_vs_fp64"] = round(out["fp64_s"] / out["mixed_s"], 3)
-        rel = {}
-        for k in fields["fp64"]:
-            a, b = fields["mixed"][k], fields["fp64"][k]
-            rel[k] = float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
-        out["mixed_vs_fp64_rel_field_diff"] = rel
+    for other in ("mixed", "mg"):
+        if "fp64" in fields and other in fields:
+            out[f"speedup_{other}_vs_fp64"] = round(out["fp64_s"] / out[f"{other}_s"], 3)
+            rel = {}
+            for k in fields["fp64"]:
+                a, b = fields[other][k], fields["fp64"][k]
+                rel[k] = float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+            out[f"{other}_vs_fp64_rel_field_diff"] = rel
+    if "mixed" in fields and "mg" in fields:
+        out["speedup_mg_vs_mixed"] = round(out["mixed_s"] / out["mg_s"], 3)
     return out
 
 
@@ -339,7 +354,10 @@ def main(argv=None):
     ap.add_argument("--ttt-n", type=int, default=127,
                     help="grid size of the mixed-vs-FP64 time-to-tolerance comparison (0: skip)")
     ap.add_argument("--ttt-stages", type=int, default=5, help="Picard stages of the time-to-tolerance run")
-    ap.add_argument("--ttt-modes", default="fp64,mixed", help="solvers of the time-to-tolerance run")
+    ap.add_argument("--ttt-mg-n", type=int, default=511,
+                    help="time to tolerance of the multigrid solver alone at this n (0: off; FP64 and mixed PT "
+                         "need hours per step there)")
+    ap.add_argument("--ttt-modes", default="fp64,mixed,mg", help="solvers of the time-to-tolerance run")
     ap.add_argument("--skip-sweeps", action="store_true",
                     help="only the reactive-wave and time-to-tolerance measurements, no T_eff line")
     ap.add_argument("--reactive-n", type=int, default=506,
@@ -508,6 +526,8 @@ def main(argv=None):
                              if args.reactive_n > 0 else None)
     out["time_to_tol"] = (time_to_tol(args.ttt_n, n_picard=args.ttt_stages, modes=tuple(args.ttt_modes.split(",")))
                           if args.ttt_n > 0 else None)
+    out["time_to_tol_mg"] = (time_to_tol(args.ttt_mg_n, n_picard=args.ttt_stages, modes=("mg",))
+                             if args.ttt_mg_n > 0 else None)
     if args.adjoint_n > 0:
         out["adjoint_run"] = adjoint_measure(args.adjoint_n, args.adjoint_steps, args.adjoint_stages,
                                              checkpoint=args.adjoint_checkpoint, mixed=args.adjoint_mixed)

@@ -61,6 +61,33 @@ __device__ __forceinline__ void prange(int J, int nf, int nc, bool face, int& lo
     }
 }
 
+// The x taps of a restriction, in registers: fine indices lo .. lo + 7 and
+// P's entries for coarse index I (a coarse grid has ceil(n/2) cells, so the
+// ratio is at most 2 and the candidate range spans at most 7 fine points).
+constexpr int MAXT = 8;
+struct Taps {
+    int lo, n;
+    double w[MAXT];
+    double sum;
+};
+__device__ __forceinline__ void taps(int J, int nf, int nc, bool face, bool skip_walls, Taps& t) {
+    int lo, hi;
+    prange(J, nf, nc, face, lo, hi);
+    if (skip_walls) {
+        lo = max(lo, 1);
+        hi = min(hi, nf - 1);
+    }
+    t.lo = lo;
+    t.n = min(hi - lo + 1, MAXT);
+    t.sum = 0.0;
+#pragma unroll
+    for (int q = 0; q < MAXT; ++q) {
+        const double w = (q < t.n) ? pweight(lo + q, J, nf, nc, face) : 0.0;
+        t.w[q] = w;
+        t.sum += w;
+    }
+}
+
 struct Ext {
     int nx, ny, nz;     // cells of the grid
     int64_t P, S;       // row and plane pitch
@@ -81,12 +108,12 @@ __global__ __launch_bounds__(TB) void k_mg_restrict(Ext f, Ext c, bool fx, bool 
             dst[o] = 0.0;
             continue;
         }
-        int xl, xh, yl, yh, zl, zh;
-        prange(I, f.nx, c.nx, fx, xl, xh);
+        // the walls' normal faces are not equations
+        Taps tx;
+        taps(I, f.nx, c.nx, fx, fx, tx);
+        int yl, yh, zl, zh;
         prange(J, f.ny, c.ny, fy, yl, yh);
         prange(K, f.nz, c.nz, fz, zl, zh);
-        // the walls' normal faces are not equations
-        if (fx) { xl = max(xl, 1); xh = min(xh, f.nx - 1); }
         if (fy) { yl = max(yl, 1); yh = min(yh, f.ny - 1); }
         if (fz) { zl = max(zl, 1); zh = min(zh, f.nz - 1); }
         double s = 0.0, ws = 0.0;
@@ -96,16 +123,20 @@ __global__ __launch_bounds__(TB) void k_mg_restrict(Ext f, Ext c, bool fx, bool 
             for (int j = yl; j <= yh; ++j) {
                 const double wy = pweight(j, J, f.ny, c.ny, fy) * wz;
                 if (wy == 0.0) continue;
-                const TS* row = src + (int64_t)k * f.S + (int64_t)j * f.P;
-                for (int i = xl; i <= xh; ++i) {
-                    const double w = pweight(i, I, f.nx, c.nx, fx) * wy;
-                    if (w == 0.0) continue;
-                    const double v = (double)row[i];
-                    s += w * (mode ? 1.0 / v : v);
-                    ws += w;
+                const TS* row = src + (int64_t)k * f.S + (int64_t)j * f.P + tx.lo;
+                double r = 0.0;
+#pragma unroll
+                for (int q = 0; q < MAXT; ++q) {
+                    if (q < tx.n) {
+                        const double v = (double)row[q];
+                        r += tx.w[q] * (mode ? 1.0 / v : v);
+                    }
                 }
+                s += wy * r;
+                ws += wy;
             }
         }
+        ws *= tx.sum;
         dst[o] = (ws > 0.0) ? (mode ? ws / s : s / ws) : 0.0;
     }
 }
@@ -120,8 +151,9 @@ __global__ __launch_bounds__(TB) void k_mg_restrict_fold(Ext f, Ext c, const flo
     const int64_t n = (int64_t)c.nx * c.ny * c.nz;
     for (int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x; t < n; t += (int64_t)gridDim.x * TB) {
         const int I = (int)(t % c.nx), J = (int)((t / c.nx) % c.ny), K = (int)(t / ((int64_t)c.nx * c.ny));
-        int xl, xh, yl, yh, zl, zh;
-        prange(I, f.nx, c.nx, false, xl, xh);
+        Taps tx;
+        taps(I, f.nx, c.nx, false, false, tx);
+        int yl, yh, zl, zh;
         prange(J, f.ny, c.ny, false, yl, yh);
         prange(K, f.nz, c.nz, false, zl, zh);
         double a = 0.0, b = 0.0, ws = 0.0;
@@ -131,16 +163,21 @@ __global__ __launch_bounds__(TB) void k_mg_restrict_fold(Ext f, Ext c, const flo
             for (int j = yl; j <= yh; ++j) {
                 const double wy = pweight(j, J, f.ny, c.ny, false) * wz;
                 if (wy == 0.0) continue;
-                const int64_t row = (int64_t)k * f.S + (int64_t)j * f.P;
-                for (int i = xl; i <= xh; ++i) {
-                    const double w = pweight(i, I, f.nx, c.nx, false) * wy;
-                    if (w == 0.0) continue;
-                    a += w * (double)rpt[row + i];
-                    b += w * (double)rpf[row + i];
-                    ws += w;
+                const int64_t row = (int64_t)k * f.S + (int64_t)j * f.P + tx.lo;
+                double ra = 0.0, rb = 0.0;
+#pragma unroll
+                for (int q = 0; q < MAXT; ++q) {
+                    if (q < tx.n) {
+                        ra += tx.w[q] * (double)rpt[row + q];
+                        rb += tx.w[q] * (double)rpf[row + q];
+                    }
                 }
+                a += wy * ra;
+                b += wy * rb;
+                ws += wy;
             }
         }
+        ws *= tx.sum;
         a /= ws;
         b /= ws;
         const int64_t o = (int64_t)K * c.S + (int64_t)J * c.P + I;

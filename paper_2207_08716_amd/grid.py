@@ -252,7 +252,7 @@ class Grid:
         code = {"fp64": abi.SOLVER_FP64, "mixed": abi.SOLVER_MIXED, "mg": abi.SOLVER_MG}[solver]
         if solver == "mixed":
             self.enable_mixed()
-        elif solver == "mg":
+        elif solver == "mg" and getattr(self, "gws", None) is None:
             self.enable_mg()
         sweeps = C.c_int64()
         rho = C.c_double()
@@ -289,8 +289,11 @@ class Grid:
 
     def solve_mg(self, rtol, max_cycles=200, **params):
         """Multigrid solve of the present Picard stage (see pt_solve_mg):
-        returns (cycles, rho, converged)."""
-        self.enable_mg(**params)
+        returns (cycles, rho, converged).  Keyword arguments rebind the
+        workspace with those parameters; without them the bound hierarchy
+        (or a default one) is used."""
+        if params or getattr(self, "gws", None) is None:
+            self.enable_mg(**params)
         cyc = C.c_int64()
         rho = C.c_double()
         st = _check(self.lib, self.h, self.lib.pt_solve_mg(self.h, float(rtol), int(max_cycles), C.byref(cyc),

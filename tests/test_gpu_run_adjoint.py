@@ -148,3 +148,59 @@ def test_run_adjoint_mixed_precision():
                                                 checkpoint=True)
     assert Jck == Jmx and aitck == aitmx
     assert np.array_equal(gradck.cpu().numpy(), gradmx)
+
+
+def _gpu_run_misfit_mg(g, phi, logk0, sensors, d_obs, steps, stages, rtol):
+    """The same Picard run with every stage solved by multigrid (the stage
+    solution does not depend on the solver); also the decompaction-switch
+    pattern (Pf > Pt) at the end."""
+    g.reset_state(phi)
+    g.set_log_k0(logk0)
+    for n in range(steps):
+        sw, rho, ok = g.picard_step(n >= 1, stages, rtol, max_iter=400, solver="mg")
+        assert ok, (n, rho)
+    return g.misfit(sensors, d_obs), (g.get("pf") > g.get("pt"))
+
+
+def test_run_adjoint_matches_finite_differences_127():
+    """The adjoint workload at its size, 127^3, with the run cut to 2 steps
+    of 5 stages: the gradient of the recorded run (mixed-precision solves to
+    1e-10) against central differences (h = 1e-4 on ln k0) at 8 random
+    cells, the forward runs solved by multigrid to 1e-11 (about the FP64
+    floor of the relative residual against the step's first residual: the
+    later stages start far below it); a cell whose
+    decompaction-switch pattern differs between the two perturbed runs would
+    be rejected (its misfit is not differentiable there)."""
+    n, steps, stages = 127, 2, 5
+    cfg, phi, logk0, sensors = _problem(n, seed=4, ns=64)
+    g = _grid(cfg, phi, logk0)
+    J0, _ = _gpu_run_misfit_mg(g, phi, logk0, sensors, np.zeros(len(sensors)), steps, stages, 1e-11)
+    d_obs = g.get("pf").ravel()[sensors] * 0.8 + 1e-4
+    g.reset_state(phi)
+    g.set_log_k0(logk0)
+    J, grad, fit, ait = g.adjoint_run(sensors, d_obs, steps, stages, rtol=1e-10, mixed=True)
+    grad = grad.cpu().numpy().copy()
+    gmax = np.abs(grad).max()
+    print(f"127^3 run adjoint: J {J} sweeps {fit} {ait} max|grad| {gmax}", flush=True)
+    assert gmax > 0
+    rng = np.random.default_rng(8)
+    cells = rng.choice(np.arange(n ** 3), size=8, replace=False)
+    h = 1e-4
+    checked = 0
+    for c in cells:
+        vals, pats = [], []
+        for sgn in (1.0, -1.0):
+            m = logk0.copy().ravel()
+            m[c] += sgn * h
+            v, pat = _gpu_run_misfit_mg(g, phi, m.reshape(logk0.shape), sensors, d_obs, steps, stages, 1e-11)
+            vals.append(v)
+            pats.append(pat)
+        if not np.array_equal(pats[0], pats[1]):
+            print("cell", c, "rejected: switch pattern differs", flush=True)
+            continue
+        fd = (vals[0] - vals[1]) / (2 * h)
+        gc = grad.ravel()[c]
+        print("cell", c, gc, fd, flush=True)
+        assert abs(gc - fd) <= 1e-6 * gmax + 1e-6 * abs(fd), (c, gc, fd)
+        checked += 1
+    assert checked >= 6
