@@ -274,6 +274,72 @@ def adjoint_measure(n, n_steps=10, n_picard=5, rtol=1e-10, ns=64, checkpoint=Fal
     return out
 
 
+def z_front(g, phi0):
+    """Top of the porosity wave: starting from the plane of the largest
+    porosity in the lower half of the box (the sources' rising waves), the
+    height (linearly interpolated between cell centres) at which the plane
+    maximum of phi first falls below 2 phi0.  A porosity layer that fluid
+    accumulating under the closed top wall may build is not connected to it
+    and is not counted."""
+    import numpy as np
+    import torch
+    lp = g.view("lp")
+    with torch.cuda.stream(g.stream):
+        # phi = 1 - exp(ln(1 - phi)): the plane maximum of phi is at the plane minimum of ln(1 - phi)
+        pmax = (1.0 - torch.exp(lp.amin(dim=(1, 2)))).cpu().numpy()
+    dz = g.phys.lz / g.nz
+    k = int(np.argmax(pmax[: g.nz // 2]))
+    if pmax[k] < 2.0 * phi0:
+        return None
+    while k + 1 < g.nz and pmax[k + 1] >= 2.0 * phi0:
+        k += 1
+    if k + 1 >= g.nz:
+        return float((k + 0.5) * dz)
+    t = (pmax[k] - 2.0 * phi0) / max(pmax[k] - pmax[k + 1], 1e-300)
+    return float((k + 0.5 + min(max(t, 0.0), 1.0)) * dz)
+
+
+def waves_run(n: int, steps: int, rtol: float = 1e-8, stages: int = 5):
+    """The porosity-wave workload (three sources in a 30^3 box, DP cap, dt =
+    5e-4) for `steps` physical steps of the Picard schedule, every stage
+    solved by multigrid to rtol: the wave front after every step and the
+    time per step."""
+    import torch
+    from paper_2207_08716_amd import inputs, schedules
+    cfg = inputs.config_waves(n)
+    g = schedules.make_grid(cfg, inputs.initial_fields(cfg))
+    # this box is 30 compaction lengths wide: grids coarser than ~2 per cell
+    # break the damped PT of the coarsest grid and the smoother needs the
+    # smaller velocity step (prototyped on the oracle): stop at 16-31 cells
+    levels, m = 1, n
+    while (m + 1) // 2 >= 16:
+        m = (m + 1) // 2
+        levels += 1
+    mg = dict(levels=levels, c_v=16.0, coarse_sweeps=400)
+    g.enable_mg(**mg)
+    fronts = [z_front(g, cfg.phys.phi0)]
+    cycles, times = [], []
+    ok_all = True
+    for s in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cyc, rho, ok = g.picard_step(s >= 1, stages, rtol, max_iter=400, solver="mg")
+        torch.cuda.synchronize()
+        times.append(round(time.perf_counter() - t0, 3))
+        cycles.append(cyc)
+        ok_all = ok_all and ok
+        fronts.append(z_front(g, cfg.phys.phi0))
+        print(f"porosity waves n={n} step {s + 1}: {cyc} V-cycles, {times[-1]} s, rho {rho:.2e}, "
+              f"z_front {fronts[-1]}", file=sys.stderr, flush=True)
+    g.close()
+    del g
+    torch.cuda.empty_cache()
+    return {"n": n, "workload": f"{n}^3 porosity-wave box (L = 30, three sources of width 1, DP cap, R0 = 100), "
+                                f"dt = {cfg.phys.dt}", "steps": steps, "picard_stages": stages, "rtol": rtol,
+            "solver": "multigrid", "mg": mg, "converged": ok_all, "v_cycles": cycles, "step_s": times,
+            "z_front": fronts, "cell_size": cfg.phys.lz / n}
+
+
 def reactive_measure(n: int, nz: int, da: float = 100.0, warm: int = 20, reps: int = 100,
                      step_n: int = 127, step_cap: int = 50000):
     """Reactive porosity waves (article 3) on n x n x nz cells: the PT
@@ -360,6 +426,9 @@ def main(argv=None):
     ap.add_argument("--ttt-modes", default="fp64,mixed,mg", help="solvers of the time-to-tolerance run")
     ap.add_argument("--skip-sweeps", action="store_true",
                     help="only the reactive-wave and time-to-tolerance measurements, no T_eff line")
+    ap.add_argument("--waves-n", type=int, default=0,
+                    help="porosity-wave run (config of 767^3 with its 20 steps) at this n, multigrid stages (0: off)")
+    ap.add_argument("--waves-steps", type=int, default=20)
     ap.add_argument("--reactive-n", type=int, default=506,
                     help="reactive porosity-wave measurement on n x n x reactive-nz cells (0: off)")
     ap.add_argument("--reactive-nz", type=int, default=2042)
@@ -388,7 +457,8 @@ def main(argv=None):
         return 1
 
     if args.skip_sweeps:
-        rec = {"reactive_waves": (reactive_measure(args.reactive_n, args.reactive_nz,
+        rec = {"porosity_waves": waves_run(args.waves_n, args.waves_steps) if args.waves_n > 0 else None,
+               "reactive_waves": (reactive_measure(args.reactive_n, args.reactive_nz,
                                                    step_n=args.reactive_step_n)
                                   if args.reactive_n > 0 else None),
                "time_to_tol": (time_to_tol(args.ttt_n, n_picard=args.ttt_stages,
