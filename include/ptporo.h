@@ -61,7 +61,7 @@
 extern "C" {
 #endif
 
-#define PT_ABI_VERSION 2
+#define PT_ABI_VERSION 3
 
 typedef struct pt_grid pt_grid;
 
@@ -80,7 +80,8 @@ typedef enum {
     PT_VX = 0, PT_VY, PT_VZ,        /* solid velocity, x/y/z-faces                    */
     PT_PT, PT_PF,                   /* total and fluid pressure (cells)               */
     PT_LP,                          /* ln(1 - phi) (cells)                            */
-    PT_RX, PT_RY, PT_RZ,            /* damped momentum residual, faces                */
+    PT_RX, PT_RY, PT_RZ,            /* damped momentum residual, faces (stored at
+                                       checks only: pt_sync_damped_residual)        */
     PT_PTO, PT_PFO, PT_LPO,         /* previous-step Pt, Pf, ln(1-phi) (cells)        */
     PT_SXX, PT_SYY, PT_SZZ,         /* stress history, cells                          */
     PT_SXY, PT_SXZ, PT_SYZ,         /* stress history, xy/xz/yz-edges                 */
@@ -292,7 +293,10 @@ pt_status pt_set_porosity(pt_grid* g, const void* phi_dev);
  * double-buffered field; mixed_copy, mixed_clean: the mixed workspace copy
  * that holds the FP32 damped residual and whether the workspace is
  * initialised (kept only if the mixed workspace is bound when set); steps,
- * dt_cum, dts: the stress-history step rule's state (PT_F_DTS_RULE). */
+ * dt_cum, dts: the stress-history step rule's state (PT_F_DTS_RULE);
+ * r_stored, v_prev: where the damped residual R of the present iterate is
+ * (the PT_RX..RZ copies, or the two copies of V; see
+ * pt_sync_damped_residual). */
 typedef struct {
     int32_t version;                /* PT_ABI_VERSION                                  */
     int32_t refreshed;
@@ -303,9 +307,24 @@ typedef struct {
     int32_t mixed_clean;
     int64_t steps;                  /* pt_begin_step calls since creation or reset     */
     double dt_cum, dts;             /* PT_F_DTS_RULE: time since the last renewal; dtS */
+    int32_t r_stored, v_prev;       /* R in PT_RX..RZ; V's other copy is V_prev       */
 } pt_counters;
 pt_status pt_get_counters(const pt_grid* g, pt_counters* out);
 pt_status pt_set_counters(pt_grid* g, const pt_counters* in);
+
+/* The damped momentum residual R of the PT velocity update (the script's
+ * damping: R' = f/rho_i + d R, V' = V + dtau_V R') is stored in PT_RX..RZ
+ * only by the sweeps that compute norms (the checks; every refresh of the
+ * schedules follows one), by every sweep of pt_solve_linear (whose tight
+ * tolerances need the stored R's digits), by every sweep with
+ * PT_F_MECHOFF, and before any
+ * call that changes the pseudo steps or V outside the sweeps (pt_refresh,
+ * pt_set_params, pt_solve_mixed, pt_solve_mg, checkpoints).  In between,
+ * the FP64 sweeps take d R from the two copies of V (d (V - V_prev) /
+ * dtau_V), which saves three of the sweep's 27 field streams.  This call
+ * stores R of the present iterate in the present copies of PT_RX..RZ (a
+ * no-op if they hold it); call it before reading them.  Enqueued. */
+pt_status pt_sync_damped_residual(pt_grid* g);
 
 /* Stage solvers of pt_picard_step. */
 #define PT_SOLVER_FP64 0    /* pt_solve_linear                               */

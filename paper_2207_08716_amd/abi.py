@@ -8,7 +8,7 @@ import os
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libptporo.so")
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 FIELDS = ("vx", "vy", "vz", "pt", "pf", "lp", "rx", "ry", "rz", "pto", "pfo", "lpo",
           "sxx", "syy", "szz", "sxy", "sxz", "syz", "fox", "foy", "foz", "mn", "k0",
@@ -49,7 +49,8 @@ class Counters(C.Structure):
                 ("ref_set", C.c_int32), ("mixed_copy", C.c_int32),
                 ("ref_v", C.c_double), ("ref_p", C.c_double),
                 ("cur", C.c_int32 * NPING), ("mixed_clean", C.c_int32),
-                ("steps", C.c_int64), ("dt_cum", C.c_double), ("dts", C.c_double)]
+                ("steps", C.c_int64), ("dt_cum", C.c_double), ("dts", C.c_double),
+                ("r_stored", C.c_int32), ("v_prev", C.c_int32)]
 
 
 EXPORTS = ["pt_create", "pt_destroy", "pt_field_elems", "pt_bind_field", "pt_workspace_size",
@@ -60,7 +61,8 @@ EXPORTS = ["pt_create", "pt_destroy", "pt_field_elems", "pt_bind_field", "pt_wor
            "pt_picard_step", "pt_mixed_workspace_size", "pt_bind_mixed_workspace", "pt_residual",
            "pt_solve_mixed", "pt_adjoint_workspace_size", "pt_bind_adjoint_workspace", "pt_set_log_k0",
            "pt_misfit", "pt_adjoint_stage", "pt_adjoint_tape_size", "pt_adjoint_run", "pt_copy", "pt_status_str", "pt_last_error", "pt_abi_version",
-           "pt_mg_workspace_size", "pt_bind_mg_workspace", "pt_mg_levels", "pt_solve_mg"]
+           "pt_mg_workspace_size", "pt_bind_mg_workspace", "pt_mg_levels", "pt_solve_mg",
+           "pt_sync_damped_residual"]
 
 # Stage solvers of pt_picard_step and the multigrid hierarchy.
 SOLVER_FP64, SOLVER_MIXED, SOLVER_MG = 0, 1, 2
@@ -173,6 +175,7 @@ def load(path: str = LIB_PATH):
     lib.pt_adjoint_run.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_int64,
                                    P(C.c_int64), C.c_int32, P(C.c_double), vp, C.c_size_t, vp,
                                    P(C.c_double), P(C.c_int64), P(C.c_int64)]
+    lib.pt_sync_damped_residual.argtypes = [vp]
     lib.pt_mg_workspace_size.argtypes = [vp, P(MgParams), P(C.c_size_t)]
     lib.pt_bind_mg_workspace.argtypes = [vp, P(MgParams), vp, C.c_size_t]
     lib.pt_mg_levels.argtypes = [vp, P(C.c_int32), P(C.c_int32)]

@@ -40,6 +40,12 @@ struct pt_grid {
     double dts = 0.0;          // PT_F_DTS_RULE: the present stress-history step
     pt_progress_fn progress = nullptr;   // per-stage report of long calls
     void* progress_user = nullptr;
+    // The FP64 sweeps store the damped residual R only at checks (see the
+    // sweep): r_ok: the present copies of PT_RX..RZ hold R of the present
+    // iterate; vp_ok: the other copies of V hold the previous iterate under
+    // the present velocity pseudo steps (so that R = (V - V_prev) / dtau_V).
+    bool r_ok = true;
+    bool vp_ok = false;
     double* gws = nullptr;     // multigrid workspace
     size_t gws_bytes = 0;
     pt_mg_params mgp{};        // multigrid parameters of the bound workspace
@@ -230,7 +236,13 @@ pt_status clear_domain(pt_grid* g) {
     return PT_OK;
 }
 
+pt_status sync_r(pt_grid* g);
+
 pt_status refresh_impl(pt_grid* g, double r_eta, double r_mu) {
+    // the pseudo steps change with mu_s: R must be stored, V_prev no longer serves
+    pt_status sst = sync_r(g);
+    if (sst != PT_OK) return sst;
+    g->vp_ok = false;
     const RefreshCoef r = make_refresh(g, r_eta, r_mu);
     const AuxPtrs a = aux(g);
     hipError_t e = launch_refresh(g->geom, g->coef, r, a, g->stream);
@@ -266,9 +278,25 @@ pt_status reduce_norms(pt_grid* g) {
     return PT_OK;
 }
 
-pt_status iteration_impl(pt_grid* g, int update_lp, int norms) {
-    const SweepPtrs<double> p = sweep_ptrs(g);
-    hipError_t e = launch_iteration(g->geom, g->coef, p, update_lp ? MD_THESIS : MD_LINEAR, norms, g->stream);
+pt_status iteration_impl(pt_grid* g, int update_lp, int norms, bool keep_r = false) {
+    SweepPtrs<double> p = sweep_ptrs(g);
+    Coef c = g->coef;
+    // the damping memory: V - V_prev when the other copy of V is the previous
+    // iterate under these pseudo steps, the stored R otherwise; R is stored
+    // by the sweeps with norms (the checks, which precede every refresh of
+    // the schedules), by every sweep with the mechanics frozen, and by every
+    // sweep of a solve to a relative residual (keep_r: near convergence
+    // V - V_prev loses the digits that a stored R keeps, which would put the
+    // attainable residual above the tightest tolerances)
+    const bool vp = g->vp_ok && !c.mech_off && !keep_r;
+    if (vp) {
+        p.rx = alt(g, PT_VX);
+        p.ry = alt(g, PT_VY);
+        p.rz = alt(g, PT_VZ);
+    }
+    c.rform = vp ? 0 : 1;
+    c.rwrite = (norms || c.mech_off || keep_r) ? 1 : 0;
+    hipError_t e = launch_iteration(g->geom, c, p, update_lp ? MD_THESIS : MD_LINEAR, norms, g->stream);
     if (e != hipSuccess) return hip_fail(g, e, "iteration");
     if (norms) {
         pt_status st = reduce_norms(g);
@@ -276,9 +304,24 @@ pt_status iteration_impl(pt_grid* g, int update_lp, int norms) {
     }
     for (int f = 0; f < PT_NPING; ++f) {
         if (f == PT_LP && !update_lp) continue;
+        if ((f == PT_RX || f == PT_RY || f == PT_RZ) && !c.rwrite) continue;
         g->cur[f] ^= 1;
     }
+    g->r_ok = c.rwrite != 0;
+    g->vp_ok = true;
     g->iter += 1;
+    return PT_OK;
+}
+
+// Store the damped residual of the present iterate in the present copies of
+// PT_RX..RZ when the sweeps carry it only in the two copies of V.
+pt_status sync_r(pt_grid* g) {
+    if (g->r_ok || !g->vp_ok) return PT_OK;
+    hipError_t e = launch_damped_residual(g->geom, g->coef, cur(g, PT_VX), cur(g, PT_VY), cur(g, PT_VZ),
+                                          alt(g, PT_VX), alt(g, PT_VY), alt(g, PT_VZ), cur(g, PT_MUS),
+                                          cur(g, PT_RX), cur(g, PT_RY), cur(g, PT_RZ), g->stream);
+    if (e != hipSuccess) return hip_fail(g, e, "damped residual");
+    g->r_ok = true;
     return PT_OK;
 }
 
@@ -442,6 +485,12 @@ pt_status pt_set_stream(pt_grid* g, void* hip_stream) {
 pt_status pt_set_params(pt_grid* g, const pt_params* params) {
     if (!g) return PT_EINVAL;
     if (!valid_params(params)) return fail(g, PT_EINVAL, "invalid parameters");
+    // the velocity pseudo steps may change: store R under the old ones
+    if (!g->broken && g->ws && bound(g, kAllCore, true)) {
+        pt_status st = sync_r(g);
+        if (st != PT_OK) return st;
+    }
+    g->vp_ok = false;
     g->prm = *params;
     make_coef(g);
     g->broken = false;
@@ -570,7 +619,7 @@ pt_status solve_linear_core(pt_grid* g, double rtol, int64_t max_iter, int64_t* 
     while (it < max_iter) {
         ++it;
         const bool want = (it == 1 && !g->ref_set) || (it % nup == 0);
-        st = iteration_impl(g, 0, want ? 1 : 0);
+        st = iteration_impl(g, 0, want ? 1 : 0, true);
         if (st != PT_OK) return st;
         if (!want) continue;
         pt_norms nm;
@@ -697,6 +746,8 @@ pt_status pt_reset_state(pt_grid* g) {
     if (e == hipSuccess) e = launch_fill(g->f[PT_ETA][0], 1.0, n, g->stream);
     if (e == hipSuccess) e = launch_fill(g->f[PT_MUS][0], p.mu0 * p.phi0 * p.cmu, n, g->stream);
     if (e != hipSuccess) return hip_fail(g, e, "reset state");
+    g->r_ok = true;     // R = 0 and V = V_prev = 0
+    g->vp_ok = true;
     // ln(1-phi) keeps its buffers: the present copy becomes copy 0 with the rest
     if (g->cur[PT_LP] != 0) {
         e = launch_copy(g->f[PT_LP][1], g->f[PT_LP][0], n, g->stream);
@@ -731,6 +782,8 @@ pt_status pt_get_counters(const pt_grid* g, pt_counters* out) {
     out->steps = g->steps;
     out->dt_cum = g->dt_cum;
     out->dts = g->dts;
+    out->r_stored = g->r_ok ? 1 : 0;
+    out->v_prev = g->vp_ok ? 1 : 0;
     return PT_OK;
 }
 
@@ -738,7 +791,8 @@ pt_status pt_set_counters(pt_grid* g, const pt_counters* in) {
     if (!g || !in) return PT_EINVAL;
     if (in->version != PT_ABI_VERSION || in->iter < 0 || (in->mixed_copy & ~1) || (in->mixed_clean & ~1) ||
         (in->refreshed & ~1) || (in->ref_set & ~1) || in->steps < 0 || !std::isfinite(in->dt_cum) ||
-        !(in->dts > 0.0 && std::isfinite(in->dts)))
+        !(in->dts > 0.0 && std::isfinite(in->dts)) || (in->r_stored & ~1) || (in->v_prev & ~1) ||
+        !(in->r_stored || in->v_prev))
         return fail(g, PT_EINVAL, "bad counters");
     for (int f = 0; f < PT_NPING; ++f)
         if (in->cur[f] & ~1) return fail(g, PT_EINVAL, "bad copy index in counters");
@@ -754,8 +808,17 @@ pt_status pt_set_counters(pt_grid* g, const pt_counters* in) {
     g->steps = in->steps;
     g->dt_cum = in->dt_cum;
     g->dts = in->dts;
+    g->r_ok = in->r_stored != 0;
+    g->vp_ok = in->v_prev != 0;
     make_coef(g);
     return PT_OK;
+}
+
+pt_status pt_sync_damped_residual(pt_grid* g) {
+    if (!g) return PT_EINVAL;
+    pt_status st = check_ready(g);
+    if (st != PT_OK) return st;
+    return sync_r(g);
 }
 
 pt_status pt_mixed_workspace_size(const pt_grid* g, size_t* bytes) {
@@ -963,6 +1026,10 @@ pt_status pt_solve_mixed(pt_grid* g, double rtol, double eta_in, int64_t max_inn
     if (st != PT_OK) return st;
     st = mixed_ready(g);
     if (st != PT_OK) return st;
+    // the corrections change V outside the sweeps: keep R stored
+    st = sync_r(g);
+    if (st != PT_OK) return st;
+    g->vp_ok = false;
     MixedTarget t;
     t.resid = sweep_ptrs(g);
     t.m = mixed_ptrs(g, 0);
@@ -1317,14 +1384,18 @@ SweepPtrs<double> mg_ptrs(pt_grid* g, int l) {
 // n linear sweeps on grid l with the smoother's (or the coarsest grid's) constants.
 pt_status mg_smooth(pt_grid* g, int l, int n) {
     const bool coarsest = l == g->mg_levels - 1;
-    const Coef c = mg_coef(g, l, coarsest);
+    Coef c = mg_coef(g, l, coarsest);
+    // the fine grid's stored R is neither read (no damping) nor written;
+    // coarse grids run the stored-R form of the sweep on their own R
+    c.rform = 1;
+    c.rwrite = l == 0 ? 0 : 1;
     for (int k = 0; k < n; ++k) {
         const SweepPtrs<double> p = mg_ptrs(g, l);
         hipError_t e = launch_iteration(g->mg_geom[l], c, p, MD_LINEAR, 0, g->stream);
         if (e != hipSuccess) return hip_fail(g, e, "multigrid sweep");
         if (l == 0) {
             for (int f = 0; f < PT_NPING; ++f)
-                if (f != PT_LP) g->cur[f] ^= 1;
+                if (f != PT_LP && f != PT_RX && f != PT_RY && f != PT_RZ) g->cur[f] ^= 1;
             g->iter += 1;
         } else {
             g->mg_cur[l] ^= 1;
@@ -1434,6 +1505,10 @@ pt_status solve_mg_core(pt_grid* g, double rtol, int64_t max_cycles, int64_t* cy
     if (!(g->prm.beta_d > 0.0) || g->prm.alpha * g->prm.alpha * g->prm.B == g->prm.alpha)
         return fail(g, PT_EINVAL, "multigrid needs beta_d > 0 and alpha B != 1 (the pressure terms carry the "
                                   "coarse right-hand side)");
+    // the cycles change V outside the damped sweeps: keep R stored
+    st = sync_r(g);
+    if (st != PT_OK) return st;
+    g->vp_ok = false;
     st = mg_coefficients(g);
     if (st != PT_OK) return st;
     double r = INFINITY;
@@ -1675,6 +1750,13 @@ pt_status recorded_step(pt_grid* g, int n, int32_t n_picard, double rtol, int64_
 // Copy the present state into (save) or out of (restore) a step checkpoint.
 pt_status checkpoint_copy(pt_grid* g, double* ck, bool save) {
     const int64_t box = mx_box(g);
+    if (save) {
+        pt_status st = sync_r(g);
+        if (st != PT_OK) return st;
+    } else {
+        g->r_ok = true;
+        g->vp_ok = false;
+    }
     for (int b = 0; b < CKPT_NBOX; ++b) {
         double* f = cur(g, CKPT_FIELDS[b]);
         hipError_t e = save ? launch_copy(f, ck + b * box, box, g->stream) : launch_copy(ck + b * box, f, box, g->stream);

@@ -268,6 +268,27 @@ __global__ __launch_bounds__(AB) void k_prepare_mixed(Geom g, MixedPtrs m) {
     m.chi32[o] = float(1.0 / (m.eta[o] * exp(m.lp[o])));
 }
 
+// Damped residual of the present iterate from the two copies of V: R =
+// (V - V_prev) / dtau_V on the interior faces, dtau_V = dtauv_c / the larger
+// mu_s of the face's two cells (the velocity pseudo step of the sweep).
+__global__ __launch_bounds__(AB) void k_damped_residual(Geom g, double dtauv_c, const double* __restrict__ vx,
+                                                        const double* __restrict__ vy, const double* __restrict__ vz,
+                                                        const double* __restrict__ vxp,
+                                                        const double* __restrict__ vyp,
+                                                        const double* __restrict__ vzp,
+                                                        const double* __restrict__ mus, double* __restrict__ rx,
+                                                        double* __restrict__ ry, double* __restrict__ rz) {
+    Idx q;
+    if (!box_index(g, (int64_t)blockIdx.x * AB + threadIdx.x, q)) return;
+    if (q.i >= g.nx || q.j >= g.ny || q.k >= g.nz) return;
+    const int64_t o = at(g, q.i, q.j, q.k);
+    const double mu = mus[o];
+    // the same operations as the sweep's stored R' = (V' - V) / dtau_V
+    if (q.i >= 1) rx[o] = (vx[o] - vxp[o]) / (dtauv_c / fmax(mu, mus[at(g, q.i - 1, q.j, q.k)]));
+    if (q.j >= 1) ry[o] = (vy[o] - vyp[o]) / (dtauv_c / fmax(mu, mus[at(g, q.i, q.j - 1, q.k)]));
+    if (q.k >= 1) rz[o] = (vz[o] - vzp[o]) / (dtauv_c / fmax(mu, mus[at(g, q.i, q.j, q.k - 1)]));
+}
+
 // Defect correction x <- x + d in FP64 (velocity faces, pressures).  The
 // correction is zero on boundary faces and outside every extent.
 __global__ __launch_bounds__(AB) void k_apply_correction(Geom g, MixedPtrs m) {
@@ -388,6 +409,14 @@ hipError_t launch_fill(double* dst, double v, int64_t n, hipStream_t s) {
         if (blocks > 256 * 16) blocks = 256 * 16;
         hipLaunchKernelGGL(k_fill, dim3((unsigned)blocks), dim3(AB), 0, s, dst, v, n);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_damped_residual(const Geom& g, const Coef& c, const double* vx, const double* vy, const double* vz,
+                                  const double* vx_p, const double* vy_p, const double* vz_p, const double* mus,
+                                  double* rx, double* ry, double* rz, hipStream_t s) {
+    hipLaunchKernelGGL(k_damped_residual, box_grid(g), dim3(AB), 0, s, g, c.dtauv_c, vx, vy, vz, vx_p, vy_p, vz_p,
+                       mus, rx, ry, rz);
     return hipGetLastError();
 }
 

@@ -27,6 +27,16 @@
 //      tile cell.
 // The next plane's loads are issued one step ahead.  Stresses and Darcy
 // fluxes never touch HBM; the iterated fields are written once.
+//
+// Damped velocity update of the FP64 sweeps (eq (19) with the script's
+// damping): R' = f/rho_i + d R, V' = V + dtau_V R'.  Between checks the
+// sweep does not store R: with dtau_V unchanged since the last iteration,
+// d R = d (V - V_prev) / dtau_V, and V_prev is the other copy of V (the one
+// this sweep overwrites), so V' = V + dtau_V f/rho_i + d (V - V_prev) needs
+// no R stream (three fewer of 27).  The first sweep after the pseudo steps
+// change (a refresh) reads the stored R instead (c.rform); sweeps that end a
+// check interval store R' = (V' - V)/dtau_V (c.rwrite), so that it is there
+// when the next refresh comes.
 #include "pt_internal.h"
 
 namespace ptk {
@@ -70,15 +80,29 @@ template <typename T>
 struct CT {
     T dxi, dyi, dzi, dt, dti, beta_d, alpha, beta_phi, rhofg, rhosg, rhobg, buoy, gdts_inv, beta_n,
         rho_i_inv, dtauv_c, dtaupt_c, dtaupf_c, dampx, dampy, dampz, ab, third, gbg_half;
-    int mech_off;
+    int mech_off, rform, rwrite;
     __device__ explicit CT(const Coef& c)
         : dxi(T(c.dxi)), dyi(T(c.dyi)), dzi(T(c.dzi)), dt(T(c.dt)), dti(T(c.dti)), beta_d(T(c.beta_d)),
           alpha(T(c.alpha)), beta_phi(T(c.beta_phi)), rhofg(T(c.rhofg)), rhosg(T(c.rhosg)),
           rhobg(T(c.rhobg)), buoy(T(c.buoy)), gdts_inv(T(c.gdts_inv)), beta_n(T(c.beta_n)),
           rho_i_inv(T(c.rho_i_inv)), dtauv_c(T(c.dtauv_c)), dtaupt_c(T(c.dtaupt_c)),
           dtaupf_c(T(c.dtaupf_c)), dampx(T(c.dampx)), dampy(T(c.dampy)), dampz(T(c.dampz)),
-          ab(T(c.ab)), third(T(c.third)), gbg_half(T(c.gbg_half)), mech_off(c.mech_off) {}
+          ab(T(c.ab)), third(T(c.third)), gbg_half(T(c.gbg_half)), mech_off(c.mech_off), rform(c.rform),
+          rwrite(c.rwrite) {}
 };
+
+// One face's damped velocity update (see the header): returns V', sets the
+// damped residual R' in r.  q: the stored R (rform) or V_prev.
+template <typename T, typename C>
+__device__ __forceinline__ T damped_update(const C& c, T v_c, T q, T f, T damp, T dtv, T& r) {
+    if (c.rform) {
+        r = f * c.rho_i_inv + damp * q;
+        return v_c + dtv * r;
+    }
+    const T v = v_c + dtv * (f * c.rho_i_inv) + damp * (v_c - q);
+    r = (v - v_c) / dtv;
+    return v;
+}
 
 // HV, if not 0, overrides the variant's block height.  BGS: the background
 // shear of eq (32) is on (a variant of its own: the plain thesis sweep has no
@@ -379,10 +403,15 @@ __global__ __launch_bounds__((sweep_bx<T, MODE, NORMS>() * (HV ? HV : sweep_by<T
                     p.res_fx[o] = float(f);
                     nm[0] = nanmax(nm[0], T(fabs(f)));
                 } else {
-                    T r = f * c.rho_i_inv + c.dampx * rx;
-                    T v = vx_c + (c.dtauv_c / fmax(mu_c, mu_w)) * r;
+                    T r, v;
+                    if constexpr (CORR) {
+                        r = f * c.rho_i_inv + c.dampx * rx;
+                        v = vx_c + (c.dtauv_c / fmax(mu_c, mu_w)) * r;
+                    } else {
+                        v = damped_update<T>(c, vx_c, rx, f, T(c.dampx), T(c.dtauv_c / fmax(mu_c, mu_w)), r);
+                    }
                     if (c.mech_off) { r = rx; v = vx_c; }
-                    p.rx_o[o] = r;
+                    if (CORR || c.rwrite) p.rx_o[o] = r;
                     p.vx_o[o] = v;
                     if (NORMS) {
                         nm[0] = nanmax(nm[0], T(fabs(f - (w - sh.w[ty][tx - 1]) * c.dxi)));
@@ -397,10 +426,15 @@ __global__ __launch_bounds__((sweep_bx<T, MODE, NORMS>() * (HV ? HV : sweep_by<T
                     p.res_fy[o] = float(f);
                     nm[0] = nanmax(nm[0], T(fabs(f)));
                 } else {
-                    T r = f * c.rho_i_inv + c.dampy * ry;
-                    T v = vy_c + (c.dtauv_c / fmax(mu_c, mu_s)) * r;
+                    T r, v;
+                    if constexpr (CORR) {
+                        r = f * c.rho_i_inv + c.dampy * ry;
+                        v = vy_c + (c.dtauv_c / fmax(mu_c, mu_s)) * r;
+                    } else {
+                        v = damped_update<T>(c, vy_c, ry, f, T(c.dampy), T(c.dtauv_c / fmax(mu_c, mu_s)), r);
+                    }
                     if (c.mech_off) { r = ry; v = vy_c; }
-                    p.ry_o[o] = r;
+                    if (CORR || c.rwrite) p.ry_o[o] = r;
                     p.vy_o[o] = v;
                     if (NORMS) {
                         nm[0] = nanmax(nm[0], T(fabs(f - (w - sh.w[ty - 1][tx]) * c.dyi)));
@@ -421,10 +455,15 @@ __global__ __launch_bounds__((sweep_bx<T, MODE, NORMS>() * (HV ? HV : sweep_by<T
                     p.res_fz[o] = float(f);
                     nm[0] = nanmax(nm[0], T(fabs(f)));
                 } else {
-                    T r = f * c.rho_i_inv + c.dampz * rz;
-                    T v = vz_c + (c.dtauv_c / fmax(mu_c, mu_p)) * r;
+                    T r, v;
+                    if constexpr (CORR) {
+                        r = f * c.rho_i_inv + c.dampz * rz;
+                        v = vz_c + (c.dtauv_c / fmax(mu_c, mu_p)) * r;
+                    } else {
+                        v = damped_update<T>(c, vz_c, rz, f, T(c.dampz), T(c.dtauv_c / fmax(mu_c, mu_p)), r);
+                    }
                     if (c.mech_off) { r = rz; v = vz_c; }
-                    p.rz_o[o] = r;
+                    if (CORR || c.rwrite) p.rz_o[o] = r;
                     p.vz_o[o] = v;
                     if (NORMS) {
                         nm[0] = nanmax(nm[0], T(fabs(f - (w - w_p) * c.dzi)));

@@ -42,6 +42,11 @@ struct Coef {
     double third;                  // 1/3
     double gbg_half;               // half the background shear rate (xy strain rate of eq (32)), 0: none
     int mech_off;
+    // FP64 sweeps: the rx..rz inputs hold the stored damped residual R
+    // (rform) or the previous velocity iterate; rwrite: store R' (see the
+    // sweep's header).  The correction sweeps always read and store R.
+    int rform = 1;
+    int rwrite = 1;
 };
 
 // Sweep modes (see iter_kernel.hip).
@@ -222,6 +227,11 @@ hipError_t launch_copy(const double* src, double* dst, int64_t n, hipStream_t s)
 // not in (0, 1).
 hipError_t launch_set_porosity(const Geom& g, const double* phi, double* lp, double* lpo, double* domain,
                                hipStream_t s);
+// Damped residual R = (V - V_prev) / dtau_V on the interior faces (dtau_V =
+// dtauv_c / the larger mu_s of the face's two cells).
+hipError_t launch_damped_residual(const Geom& g, const Coef& c, const double* vx, const double* vy, const double* vz,
+                                  const double* vx_p, const double* vy_p, const double* vz_p, const double* mus,
+                                  double* rx, double* ry, double* rz, hipStream_t s);
 // n doubles <- v (a kernel, so that the clear can sit in a captured graph).
 hipError_t launch_fill(double* dst, double v, int64_t n, hipStream_t s);
 

@@ -152,8 +152,11 @@ class Grid:
 
     # ---- state access --------------------------------------------------------
     def tensor(self, name):
-        """Device tensor (padded box) holding the present value of a field."""
+        """Device tensor (padded box) holding the present value of a field
+        (the damped residual is stored first, see pt_sync_damped_residual)."""
         fid = abi.FIELD_ID[name]
+        if name in ("rx", "ry", "rz"):
+            _check(self.lib, self.h, self.lib.pt_sync_damped_residual(self.h), "sync damped residual")
         cp = C.c_int32()
         _check(self.lib, self.h, self.lib.pt_current(self.h, fid, C.byref(cp)), "current")
         return self.buf[name][cp.value]

@@ -202,7 +202,10 @@ def test_counters_round_trip_on_the_host(lib):
         c = abi.Counters()
         assert lib.pt_get_counters(h1, C.byref(c)) == 0
         assert c.version == abi.ABI_VERSION and c.iter == 0 and c.ref_set == 0 and list(c.cur) == [0] * abi.NPING
+        # a new handle: R is in its fields, V's other copy holds no iterate
+        assert (c.r_stored, c.v_prev) == (1, 0)
         c.iter, c.refreshed, c.ref_set, c.ref_v, c.ref_p = 37, 1, 1, 2.5, 0.125
+        c.r_stored, c.v_prev = 0, 1
         c.cur[0], c.cur[5], c.mixed_copy = 1, 1, 1
         assert lib.pt_set_counters(h2, C.byref(c)) == 0
         d = abi.Counters()
@@ -210,11 +213,12 @@ def test_counters_round_trip_on_the_host(lib):
         assert (d.iter, d.refreshed, d.ref_set, d.ref_v, d.ref_p) == (37, 1, 1, 2.5, 0.125)
         assert list(d.cur) == [1, 0, 0, 0, 0, 1, 0, 0, 0] and d.mixed_copy == 1
         assert d.mixed_clean == 0                       # no mixed workspace bound
+        assert (d.r_stored, d.v_prev) == (0, 1)
         gv, gp = C.c_double(), C.c_double()
         assert lib.pt_residual_reference(h2, C.byref(gv), C.byref(gp)) == 0 and (gv.value, gp.value) == (2.5, 0.125)
         cur = C.c_int32()
         assert lib.pt_current(h2, 5, C.byref(cur)) == 0 and cur.value == 1
-        for field, value in (("version", 99), ("iter", -1), ("mixed_copy", 2)):
+        for field, value in (("version", 99), ("iter", -1), ("mixed_copy", 2), ("r_stored", 2), ("v_prev", 0)):
             bad = abi.Counters()
             C.memmove(C.byref(bad), C.byref(c), C.sizeof(c))
             setattr(bad, field, value)
