@@ -1385,12 +1385,18 @@ SweepPtrs<double> mg_ptrs(pt_grid* g, int l) {
 pt_status mg_smooth(pt_grid* g, int l, int n) {
     const bool coarsest = l == g->mg_levels - 1;
     Coef c = mg_coef(g, l, coarsest);
-    // the fine grid's stored R is neither read (no damping) nor written;
-    // coarse grids run the stored-R form of the sweep on their own R
+    // the smoother has no damping: R is neither needed nor stored, and its
+    // input slots take the present V (a cache hit instead of three streams);
+    // the coarsest grid's damped sweeps run the stored-R form on its own R
     c.rform = 1;
-    c.rwrite = l == 0 ? 0 : 1;
+    c.rwrite = coarsest ? 1 : 0;
     for (int k = 0; k < n; ++k) {
-        const SweepPtrs<double> p = mg_ptrs(g, l);
+        SweepPtrs<double> p = mg_ptrs(g, l);
+        if (!coarsest) {
+            p.rx = p.vx;
+            p.ry = p.vy;
+            p.rz = p.vz;
+        }
         hipError_t e = launch_iteration(g->mg_geom[l], c, p, MD_LINEAR, 0, g->stream);
         if (e != hipSuccess) return hip_fail(g, e, "multigrid sweep");
         if (l == 0) {
