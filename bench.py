@@ -116,17 +116,20 @@ def cpu_baseline(cfg, fields, ctx_n=255, single_n=64):
     }
 
 
-def time_to_tol(n: int, rtol: float = 1e-8, n_picard: int = 5, eta_in: float = 1e-4, modes=("fp64", "mixed", "mg")):
+def time_to_tol(n: int, rtol: float = 1e-8, n_picard: int = 5, eta_in: float = 1e-4, modes=("fp64", "mixed", "mg"),
+                workload: str = "anomaly"):
     """Wall time of one physical step of the Picard schedule (n_picard stages,
     each linear solve to a relative residual rtol) on the mixed workload at n^3:
     FP64 PT sweeps, FP32 sweeps inside FP64 defect correction, and FP64
     multigrid V-cycles, on the same GPU, from the same initial state
-    (n_picard = 1: the step's first stage alone; modes: any of the three)."""
+    (n_picard = 1: the step's first stage alone; modes: any of the three;
+    workload "production": the production box of Table 2 on n x n x 2n cells,
+    its first step)."""
     import numpy as np
     import torch
     from paper_2207_08716_amd import inputs, schedules
 
-    cfg = inputs.config_mixed(n)
+    cfg = inputs.config_production(n, n, 2 * n) if workload == "production" else inputs.config_mixed(n)
     f = inputs.initial_fields(cfg)
     # load every kernel once on a small grid so that timing excludes code loading
     warm_cfg = inputs.config_mixed(16)
@@ -143,8 +146,10 @@ def time_to_tol(n: int, rtol: float = 1e-8, n_picard: int = 5, eta_in: float = 1
 
     chunk, max_fp64, max_outer = 20000, 1_000_000, 40
     what = "one Picard step" if n_picard == 5 else f"the first {n_picard} Picard stage(s) of a step"
+    wl = (f"{cfg.nx}x{cfg.ny}x{cfg.nz} production box of Table 2 (background shear, power law, R0 = 2000)"
+          if workload == "production" else f"{n}^3 two-anomaly grid, lognormal k0, DP cap")
     out = {"n": n, "rtol": rtol, "picard_stages": n_picard, "eta_in": eta_in,
-           "dt": cfg.phys.dt, "workload": f"{n}^3 two-anomaly grid, lognormal k0, DP cap; {what}"}
+           "dt": cfg.phys.dt, "workload": f"{wl}; {what}"}
     fields = {}
     for mode in modes:
         g = schedules.make_grid(cfg, f)
@@ -420,6 +425,8 @@ def main(argv=None):
     ap.add_argument("--ttt-n", type=int, default=127,
                     help="grid size of the mixed-vs-FP64 time-to-tolerance comparison (0: skip)")
     ap.add_argument("--ttt-stages", type=int, default=5, help="Picard stages of the time-to-tolerance run")
+    ap.add_argument("--ttt-workload", choices=("anomaly", "production"), default="anomaly",
+                    help="workload of the time-to-tolerance runs")
     ap.add_argument("--ttt-mg-n", type=int, default=511,
                     help="time to tolerance of the multigrid solver alone at this n (0: off; FP64 and mixed PT "
                          "need hours per step there)")
@@ -462,7 +469,7 @@ def main(argv=None):
                                                    step_n=args.reactive_step_n)
                                   if args.reactive_n > 0 else None),
                "time_to_tol": (time_to_tol(args.ttt_n, n_picard=args.ttt_stages,
-                                           modes=tuple(args.ttt_modes.split(",")))
+                                           modes=tuple(args.ttt_modes.split(",")), workload=args.ttt_workload)
                                if args.ttt_n > 0 else None)}
         print(json.dumps(rec), flush=True)
         return 0
