@@ -202,5 +202,8 @@ def test_run_adjoint_matches_finite_differences_127():
         gc = grad.ravel()[c]
         print("cell", c, gc, fd, flush=True)
         assert abs(gc - fd) <= 1e-6 * gmax + 1e-6 * abs(fd), (c, gc, fd)
+        # and cell by cell: the difference is the central difference's
+        # O(h^2) error and the forward solves' tolerance, far below 1e-4
+        assert abs(gc - fd) <= 1e-4 * abs(fd), (c, gc, fd)
         checked += 1
     assert checked >= 6
