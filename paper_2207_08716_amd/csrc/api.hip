@@ -856,20 +856,34 @@ pt_status pt_residual(pt_grid* g) {
 
 namespace {
 
-pt_status correction_sweep(pt_grid* g, int cp, int norms) {
+// One FP32 correction sweep: the correction d in copy cp, its damped
+// residual R_d in copy cr.  As in the FP64 sweeps, R_d is read only by the
+// first sweep of a correction (rform; d restarts at zero, so d - d_prev says
+// nothing) and stored only by the sweeps that end a check interval or the
+// correction (rwrite); in between the sweep takes it from the two copies of
+// d, three streams fewer.
+pt_status correction_sweep(pt_grid* g, int cp, int cr, int norms, bool rform, bool rwrite) {
     SweepPtrs<float> p{};
     const int src = cp ? 8 : 0, dst = cp ? 0 : 8;
+    const int rsrc = cr ? 8 : 0, rdst = cr ? 0 : 8;
     p.vx = mx(g, src + 0); p.vy = mx(g, src + 1); p.vz = mx(g, src + 2);
     p.pt = mx(g, src + 3); p.pf = mx(g, src + 4);
-    p.rx = mx(g, src + 5); p.ry = mx(g, src + 6); p.rz = mx(g, src + 7);
+    if (rform) {
+        p.rx = mx(g, rsrc + 5); p.ry = mx(g, rsrc + 6); p.rz = mx(g, rsrc + 7);
+    } else {
+        p.rx = mx(g, dst + 0); p.ry = mx(g, dst + 1); p.rz = mx(g, dst + 2);
+    }
     p.vx_o = mx(g, dst + 0); p.vy_o = mx(g, dst + 1); p.vz_o = mx(g, dst + 2);
     p.pt_o = mx(g, dst + 3); p.pf_o = mx(g, dst + 4);
-    p.rx_o = mx(g, dst + 5); p.ry_o = mx(g, dst + 6); p.rz_o = mx(g, dst + 7);
+    p.rx_o = mx(g, rdst + 5); p.ry_o = mx(g, rdst + 6); p.rz_o = mx(g, rdst + 7);
     p.fox = mx(g, MX_RES + 0); p.foy = mx(g, MX_RES + 1); p.foz = mx(g, MX_RES + 2);
     p.pto = mx(g, MX_RES + 3); p.pfo = mx(g, MX_RES + 4);
     p.kc = mx(g, 21); p.mus = mx(g, 22); p.eta = mx(g, 23);
     p.partials = norm_area(g);
-    hipError_t e = launch_correction(g->geom, g->coef, p, norms, g->stream);
+    Coef c = g->coef;
+    c.rform = rform ? 1 : 0;
+    c.rwrite = rwrite ? 1 : 0;
+    hipError_t e = launch_correction(g->geom, c, p, norms, g->stream);
     if (e != hipSuccess) return hip_fail(g, e, "correction sweep");
     if (norms) return reduce_norms(g);
     return PT_OK;
@@ -964,16 +978,19 @@ pt_status mixed_core(pt_grid* g, const MixedTarget& t, double rtol, double eta_i
         // previous correction: with it, the PT iteration on A d = -r(x) is
         // the continuation of the PT iteration on x itself (same operator,
         // same pseudo-steps), so a restart costs no convergence
-        int cp = copy;
+        int cp = copy, cr = copy;
         e = hipMemsetAsync(mx(g, cp ? 8 : 0), 0, 5 * box_bytes, g->stream);
         if (e != hipSuccess) return hip_fail(g, e, "correction clear");
         double best = INFINITY;
         int since_best = 0;
         for (int64_t it = 1; it <= max_inner; ++it) {
             const bool chk = (it % nup == 0);
-            st = correction_sweep(g, cp, chk ? 1 : 0);
+            // every exit of this loop follows a check or the last sweep: R_d stored there
+            const bool rwrite = chk || it == max_inner;
+            st = correction_sweep(g, cp, cr, chk ? 1 : 0, it == 1, rwrite);
             if (st != PT_OK) return st;
             cp ^= 1;
+            if (rwrite) cr ^= 1;
             ++inner_total;
             if (chk) {
                 pt_norms ni;
@@ -994,7 +1011,9 @@ pt_status mixed_core(pt_grid* g, const MixedTarget& t, double rtol, double eta_i
         m.dpt = mx(g, b + 3); m.dpf = mx(g, b + 4);
         e = launch_apply_correction(g->geom, m, g->stream);
         if (e != hipSuccess) return hip_fail(g, e, "apply correction");
-        copy = cp;
+        // the next correction's d starts in the copy that holds R_d (either
+        // copy serves: d is cleared, R_d lives in boxes of its own)
+        copy = cr;
         ++outer;
     }
     if (inner_iters) *inner_iters += inner_total;

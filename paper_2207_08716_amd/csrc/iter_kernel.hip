@@ -36,7 +36,8 @@
 // no R stream (three fewer of 27).  The first sweep after the pseudo steps
 // change (a refresh) reads the stored R instead (c.rform); sweeps that end a
 // check interval store R' = (V' - V)/dtau_V (c.rwrite), so that it is there
-// when the next refresh comes.
+// when the next refresh comes.  The FP32 correction sweeps do the same with
+// the damped residual of the correction.
 #include "pt_internal.h"
 
 namespace ptk {
@@ -403,15 +404,10 @@ __global__ __launch_bounds__((sweep_bx<T, MODE, NORMS>() * (HV ? HV : sweep_by<T
                     p.res_fx[o] = float(f);
                     nm[0] = nanmax(nm[0], T(fabs(f)));
                 } else {
-                    T r, v;
-                    if constexpr (CORR) {
-                        r = f * c.rho_i_inv + c.dampx * rx;
-                        v = vx_c + (c.dtauv_c / fmax(mu_c, mu_w)) * r;
-                    } else {
-                        v = damped_update<T>(c, vx_c, rx, f, T(c.dampx), T(c.dtauv_c / fmax(mu_c, mu_w)), r);
-                    }
+                    T r;
+                    T v = damped_update<T>(c, vx_c, rx, f, T(c.dampx), T(c.dtauv_c / fmax(mu_c, mu_w)), r);
                     if (c.mech_off) { r = rx; v = vx_c; }
-                    if (CORR || c.rwrite) p.rx_o[o] = r;
+                    if (c.rwrite) p.rx_o[o] = r;
                     p.vx_o[o] = v;
                     if (NORMS) {
                         nm[0] = nanmax(nm[0], T(fabs(f - (w - sh.w[ty][tx - 1]) * c.dxi)));
@@ -426,15 +422,10 @@ __global__ __launch_bounds__((sweep_bx<T, MODE, NORMS>() * (HV ? HV : sweep_by<T
                     p.res_fy[o] = float(f);
                     nm[0] = nanmax(nm[0], T(fabs(f)));
                 } else {
-                    T r, v;
-                    if constexpr (CORR) {
-                        r = f * c.rho_i_inv + c.dampy * ry;
-                        v = vy_c + (c.dtauv_c / fmax(mu_c, mu_s)) * r;
-                    } else {
-                        v = damped_update<T>(c, vy_c, ry, f, T(c.dampy), T(c.dtauv_c / fmax(mu_c, mu_s)), r);
-                    }
+                    T r;
+                    T v = damped_update<T>(c, vy_c, ry, f, T(c.dampy), T(c.dtauv_c / fmax(mu_c, mu_s)), r);
                     if (c.mech_off) { r = ry; v = vy_c; }
-                    if (CORR || c.rwrite) p.ry_o[o] = r;
+                    if (c.rwrite) p.ry_o[o] = r;
                     p.vy_o[o] = v;
                     if (NORMS) {
                         nm[0] = nanmax(nm[0], T(fabs(f - (w - sh.w[ty - 1][tx]) * c.dyi)));
@@ -455,15 +446,10 @@ __global__ __launch_bounds__((sweep_bx<T, MODE, NORMS>() * (HV ? HV : sweep_by<T
                     p.res_fz[o] = float(f);
                     nm[0] = nanmax(nm[0], T(fabs(f)));
                 } else {
-                    T r, v;
-                    if constexpr (CORR) {
-                        r = f * c.rho_i_inv + c.dampz * rz;
-                        v = vz_c + (c.dtauv_c / fmax(mu_c, mu_p)) * r;
-                    } else {
-                        v = damped_update<T>(c, vz_c, rz, f, T(c.dampz), T(c.dtauv_c / fmax(mu_c, mu_p)), r);
-                    }
+                    T r;
+                    T v = damped_update<T>(c, vz_c, rz, f, T(c.dampz), T(c.dtauv_c / fmax(mu_c, mu_p)), r);
                     if (c.mech_off) { r = rz; v = vz_c; }
-                    if (CORR || c.rwrite) p.rz_o[o] = r;
+                    if (c.rwrite) p.rz_o[o] = r;
                     p.vz_o[o] = v;
                     if (NORMS) {
                         nm[0] = nanmax(nm[0], T(fabs(f - (w - w_p) * c.dzi)));
