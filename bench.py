@@ -510,6 +510,9 @@ def main(argv=None):
     norms = g.last_norms() if args.steps >= 1 else None
     t_it = t_steps / (args.steps * nup)
     value = teff.t_eff_gbs(cfg.ncell, 8, t_it)
+    # spread of the same measurement: 5 further blocks of 7 refresh cycles
+    # (105 iterations each), after the timed region
+    blocks = sorted(timed(lambda k: g.iterate(k * nup), 7) / (7 * nup) for _ in range(5))
 
     # ---- dominant kernel alone: the fused sweep (thesis variant), measured
     # with HIP events on the solver's stream over back-to-back launches ------
@@ -590,6 +593,8 @@ def main(argv=None):
                                   "algorithmic_bytes_per_launch": a_eff32},
         "copy_gbs": round(copy_gbs, 1),
         "wall_s_timed": round(t_wall, 3),
+        "t_it_ms_5_blocks": {"median": round(blocks[2] * 1e3, 4), "min": round(blocks[0] * 1e3, 4),
+                             "max": round(blocks[-1] * 1e3, 4), "iterations_per_block": 7 * nup},
         "norms_last_check": norms,
         "decompaction_flips": flips,
         "weakened_cell_fraction": round(weakened, 6),
