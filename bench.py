@@ -31,6 +31,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "PT-iter T_eff GB/s (% HBM peak) at 511³; mixed vs FP64 time-to-tol 1e-8"
+# Directions kept by the Krylov-accelerated multigrid ("mgk"): 8 on the
+# stage systems measured (4 and 2 stall on some of them; the memory is
+# 5 (m + 1) FP64 and FP32 fine boxes)
+MG_KRYLOV = 8
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_iter_thesis_511.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2207_08716_amd", "csrc", "iter_kernel.hip")
@@ -140,6 +144,7 @@ def time_to_tol(n: int, rtol: float = 1e-8, n_picard: int = 5, eta_in: float = 1
     w.solve_linear(1e-2, 1000)
     w.solve_mixed(1e-2, 1e-1, 1000, 2)
     w.solve_mg(1e-2, 5)
+    w.solve_mg(1e-2, 5, krylov=MG_KRYLOV)
     w.porosity_step()
     torch.cuda.synchronize()
     del w
@@ -155,8 +160,8 @@ def time_to_tol(n: int, rtol: float = 1e-8, n_picard: int = 5, eta_in: float = 1
         g = schedules.make_grid(cfg, f)
         if mode == "mixed":
             g.enable_mixed()
-        elif mode == "mg":
-            g.enable_mg()
+        elif mode in ("mg", "mgk"):
+            g.enable_mg(krylov=MG_KRYLOV if mode == "mgk" else 0)
             out["mg_levels"] = g.mg_levels()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -176,12 +181,13 @@ def time_to_tol(n: int, rtol: float = 1e-8, n_picard: int = 5, eta_in: float = 1
                     print(f"time-to-tol fp64 n={n} stage {len(its) + 1}: {total} iterations rho={rho:.2e}",
                           file=sys.stderr, flush=True)
                 its.append(total)
-            elif mode == "mg":
+            elif mode in ("mg", "mgk"):
+                # (a call starts the Krylov subspace afresh: longer chunks)
                 total, ok = 0, False
                 while not ok and total < 2000:
-                    cyc, rho, ok = g.solve_mg(rtol, 10)
+                    cyc, rho, ok = g.solve_mg(rtol, 10 if mode == "mg" else 50)
                     total += cyc
-                    print(f"time-to-tol mg n={n} stage {len(its) + 1}: {total} V-cycles rho={rho:.2e}",
+                    print(f"time-to-tol {mode} n={n} stage {len(its) + 1}: {total} V-cycles rho={rho:.2e}",
                           file=sys.stderr, flush=True)
                 its.append(total)
             else:
@@ -205,7 +211,7 @@ def time_to_tol(n: int, rtol: float = 1e-8, n_picard: int = 5, eta_in: float = 1
         g.close()
         del g
         torch.cuda.empty_cache()
-    for other in ("mixed", "mg"):
+    for other in ("mixed", "mg", "mgk"):
         if "fp64" in fields and other in fields:
             out[f"speedup_{other}_vs_fp64"] = round(out["fp64_s"] / out[f"{other}_s"], 3)
             rel = {}
@@ -215,6 +221,12 @@ def time_to_tol(n: int, rtol: float = 1e-8, n_picard: int = 5, eta_in: float = 1
             out[f"{other}_vs_fp64_rel_field_diff"] = rel
     if "mixed" in fields and "mg" in fields:
         out["speedup_mg_vs_mixed"] = round(out["mixed_s"] / out["mg_s"], 3)
+    if "mg" in fields and "mgk" in fields:
+        rel = {}
+        for k in fields["mg"]:
+            a, b = fields["mgk"][k], fields["mg"][k]
+            rel[k] = float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+        out["mgk_vs_mg_rel_field_diff"] = rel
     return out
 
 
@@ -320,7 +332,7 @@ def waves_run(n: int, steps: int, rtol: float = 1e-8, stages: int = 5):
     while (m + 1) // 2 >= 16:
         m = (m + 1) // 2
         levels += 1
-    mg = dict(levels=levels, c_v=16.0, coarse_sweeps=400)
+    mg = dict(levels=levels, c_v=16.0, coarse_sweeps=400, krylov=MG_KRYLOV)
     g.enable_mg(**mg)
     fronts = [z_front(g, cfg.phys.phi0)]
     cycles, times = [], []
@@ -430,7 +442,9 @@ def main(argv=None):
     ap.add_argument("--ttt-mg-n", type=int, default=511,
                     help="time to tolerance of the multigrid solver alone at this n (0: off; FP64 and mixed PT "
                          "need hours per step there)")
-    ap.add_argument("--ttt-modes", default="fp64,mixed,mg", help="solvers of the time-to-tolerance run")
+    ap.add_argument("--ttt-modes", default="fp64,mixed,mg,mgk", help="solvers of the time-to-tolerance run "
+                    "(mg: multigrid cycles, mgk: Krylov-accelerated cycles)")
+    ap.add_argument("--ttt-mg-modes", default="mg,mgk", help="solvers of the full-size multigrid run")
     ap.add_argument("--skip-sweeps", action="store_true",
                     help="only the reactive-wave and time-to-tolerance measurements, no T_eff line")
     ap.add_argument("--waves-n", type=int, default=0,
@@ -608,7 +622,8 @@ def main(argv=None):
                              if args.reactive_n > 0 else None)
     out["time_to_tol"] = (time_to_tol(args.ttt_n, n_picard=args.ttt_stages, modes=tuple(args.ttt_modes.split(",")))
                           if args.ttt_n > 0 else None)
-    out["time_to_tol_mg"] = (time_to_tol(args.ttt_mg_n, n_picard=args.ttt_stages, modes=("mg",))
+    out["time_to_tol_mg"] = (time_to_tol(args.ttt_mg_n, n_picard=args.ttt_stages,
+                                         modes=tuple(args.ttt_mg_modes.split(",")), workload=args.ttt_workload)
                              if args.ttt_mg_n > 0 else None)
     if args.adjoint_n > 0:
         out["adjoint_run"] = adjoint_measure(args.adjoint_n, args.adjoint_steps, args.adjoint_stages,

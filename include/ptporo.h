@@ -61,7 +61,7 @@
 extern "C" {
 #endif
 
-#define PT_ABI_VERSION 3
+#define PT_ABI_VERSION 4
 
 typedef struct pt_grid pt_grid;
 
@@ -370,11 +370,16 @@ typedef struct {
     int32_t coarse_sweeps;    /* damped PT sweeps on the coarsest grid (>= 1)        */
     int32_t n_pt;             /* the smoother's Pt pseudo step mu_s / n_pt (>= 1)    */
     double c_v, c_pf;         /* the smoother's pseudo-step factors                  */
+    int32_t krylov;           /* 0: plain cycles; 1..PT_MG_MAX_KRYLOV: Krylov
+                                 acceleration keeping that many directions         */
+    int32_t reserved;         /* 0                                                   */
 } pt_mg_params;
+#define PT_MG_MAX_KRYLOV 8
 
 /* Workspace of a hierarchy (the fine grid's FP32 residual, and per coarse
  * grid 25 FP64 boxes plus, above the coarsest, 5 FP32 boxes: about a
- * quarter of the fine grid's fields): query, then bind a device buffer
+ * quarter of the fine grid's fields; with krylov = m, a further 5 (m + 1)
+ * FP64 and 5 (m + 1) FP32 fine boxes): query, then bind a device buffer
  * (256-byte aligned) of at least that size; binding clears it (enqueued).
  * PT_EINVAL if the grid cannot be coarsened to the requested levels. */
 pt_status pt_mg_workspace_size(const pt_grid* g, const pt_mg_params* mg, size_t* bytes);
@@ -390,7 +395,20 @@ pt_status pt_mg_levels(const pt_grid* g, int32_t* levels, int32_t* counts);
  * rho <= rtol or after max_cycles coarse corrections; coarse-grid
  * correction; nu2 sweeps }.  cycles: coarse corrections done.
  * Synchronises once per cycle.  PT_ENOTCONV if rtol is not met (the state
- * is valid; calling again continues). */
+ * is valid; calling again continues).
+ *
+ * With krylov = m > 0 the cycles are Krylov-accelerated (the stage
+ * system and the cycle are linear): after nu1 sweeps, each step runs one
+ * cycle from the iterate x (correction, nu2 + nu1 sweeps) to y, and moves
+ * to x' = y + sum_s gamma_s p_s, gamma minimising the residual of x' in the
+ * residual norm weighted by the step reference over the stored directions
+ * p_s (at most m: the cycles' own steps y - x, made orthogonal in that
+ * norm through their images A(y - x) = r(x) - r(y)).  The cycle's step
+ * itself is never scaled down: single cycles can raise the residual norm
+ * before the following ones reduce it.  Directions are FP64, their images
+ * FP32.  The stop is rho of x' or of y (then y is kept), <= rtol; each
+ * step costs one cycle, two residuals and two vector passes (four
+ * synchronisations).  A call starts without stored directions. */
 pt_status pt_solve_mg(pt_grid* g, double rtol, int64_t max_cycles, int64_t* cycles, double* rho);
 
 /* ---- Mixed precision (FP32 sweeps inside FP64 defect correction) --------

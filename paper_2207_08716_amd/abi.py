@@ -8,7 +8,7 @@ import os
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libptporo.so")
 
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 FIELDS = ("vx", "vy", "vz", "pt", "pf", "lp", "rx", "ry", "rz", "pto", "pfo", "lpo",
           "sxx", "syy", "szz", "sxy", "sxz", "syz", "fox", "foy", "foz", "mn", "k0",
@@ -67,21 +67,24 @@ EXPORTS = ["pt_create", "pt_destroy", "pt_field_elems", "pt_bind_field", "pt_wor
 # Stage solvers of pt_picard_step and the multigrid hierarchy.
 SOLVER_FP64, SOLVER_MIXED, SOLVER_MG = 0, 1, 2
 MG_MAX_LEVELS = 12
+MG_MAX_KRYLOV = 8
 
 
 class MgParams(C.Structure):
     _fields_ = [("version", C.c_int32), ("levels", C.c_int32), ("nu1", C.c_int32), ("nu2", C.c_int32),
-                ("coarse_sweeps", C.c_int32), ("n_pt", C.c_int32), ("c_v", C.c_double), ("c_pf", C.c_double)]
+                ("coarse_sweeps", C.c_int32), ("n_pt", C.c_int32), ("c_v", C.c_double), ("c_pf", C.c_double),
+                ("krylov", C.c_int32), ("reserved", C.c_int32)]
 
 
-def mg_params(levels=0, nu1=4, nu2=4, coarse_sweeps=50, n_pt=4, c_v=8.0, c_pf=6.1) -> MgParams:
+def mg_params(levels=0, nu1=4, nu2=4, coarse_sweeps=50, n_pt=4, c_v=8.0, c_pf=6.1, krylov=0) -> MgParams:
     """Multigrid parameters (pt_mg_params).  Defaults, measured on the mixed
     workload at 511^3 (a Picard step of 5 stages to 1e-8): the smoother
     diverges at c_v = 5 and at n_pt = 2, so c_v = 8 keeps a margin (80
     V-cycles, 6.55 s, against 77 and 6.32 s at c_v = 6.1); n_pt = 6 would
-    cost 5-25 % more cycles."""
+    cost 5-25 % more cycles.  krylov = m > 0: Krylov acceleration of the
+    cycles with m stored directions."""
     return MgParams(ABI_VERSION, int(levels), int(nu1), int(nu2), int(coarse_sweeps), int(n_pt),
-                    float(c_v), float(c_pf))
+                    float(c_v), float(c_pf), int(krylov), 0)
 
 
 # Reactive porosity waves (include/ptwaves.h).

@@ -9,7 +9,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libptporo.so")
 SOURCES = ["api.hip", "iter_kernel.hip", "refresh_kernel.hip", "aux_kernels.hip", "adjoint_kernels.hip", "waves.hip",
-           "mg_kernels.hip"]
+           "mg_kernels.hip", "krylov_kernels.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",

@@ -1279,6 +1279,7 @@ bool mg_valid(const pt_mg_params* m) {
     if (m->nu1 < 1 || m->nu2 < 0 || m->nu1 > 1000 || m->nu2 > 1000) return false;
     if (m->coarse_sweeps < 1 || m->coarse_sweeps > 1000000 || m->n_pt < 1) return false;
     if (!(m->c_v > 0.0 && std::isfinite(m->c_v)) || !(m->c_pf > 0.0 && std::isfinite(m->c_pf))) return false;
+    if (m->krylov < 0 || m->krylov > PT_MG_MAX_KRYLOV || m->reserved != 0) return false;
     return true;
 }
 
@@ -1307,16 +1308,30 @@ int64_t mg_part_blocks(const Geom* geo, int L) {
 }
 int64_t mg_part_doubles(const Geom* geo, int L) { return (mg_part_blocks(geo, L) * NNORM + NNORM + 1 + 31) / 32 * 32; }
 
-size_t mg_needed(const pt_grid* g, const pt_mg_params& m) {
-    Geom geo[PT_MG_MAX_LEVELS];
-    const int L = mg_plan(g, m, geo);
-    if (!L) return 0;
-    int64_t n = mg_res_doubles(geo[0]);
-    n += mg_part_doubles(geo, L);
+// Doubles of the hierarchy's pieces (without the Krylov vectors).
+int64_t mg_core_doubles(const Geom* geo, int L) {
+    int64_t n = mg_res_doubles(geo[0]) + mg_part_doubles(geo, L);
     for (int l = 1; l < L; ++l) {
         n += MG_NB * mg_stride(geo[l]);
         if (l < L - 1) n += mg_res_doubles(geo[l]);
     }
+    return n;
+}
+
+// Krylov vectors after them: the saved iterate and m directions p (5 FP64
+// fine boxes each), the residual of the cycle's result and m images A p (5
+// FP32 fine boxes each), and the partial sums of the inner products.
+int64_t kry_part_doubles() { return ((int64_t)KRY_BLOCKS * KRY_SLOTS + KRY_SLOTS + 31) / 32 * 32; }
+int64_t kry_doubles(const Geom& f, int m) {
+    return 5 * (1 + (int64_t)m) * mg_stride(f) + (1 + (int64_t)m) * mg_res_doubles(f) + kry_part_doubles();
+}
+
+size_t mg_needed(const pt_grid* g, const pt_mg_params& m) {
+    Geom geo[PT_MG_MAX_LEVELS];
+    const int L = mg_plan(g, m, geo);
+    if (!L) return 0;
+    int64_t n = mg_core_doubles(geo, L);
+    if (m.krylov > 0) n += kry_doubles(geo[0], m.krylov);
     return (size_t)n * sizeof(double);
 }
 
@@ -1331,6 +1346,20 @@ float* mg_res(pt_grid* g, int l, int q) {
     return reinterpret_cast<float*>(base) + (int64_t)q * (box_of(g->mg_geom[l]) + 64);
 }
 double* mg_partials(pt_grid* g) { return g->gws + mg_res_doubles(g->mg_geom[0]); }
+double* kry_base(pt_grid* g) { return g->gws + mg_core_doubles(g->mg_geom, g->mg_levels); }
+double* kry_x(pt_grid* g, int q) { return kry_base(g) + (int64_t)q * mg_stride(g->mg_geom[0]); }
+double* kry_p(pt_grid* g, int s, int q) { return kry_base(g) + (5 + 5 * (int64_t)s + q) * mg_stride(g->mg_geom[0]); }
+// v = 0: residual of the cycle's result; 1 + s: A p_s.
+float* kry_vec(pt_grid* g, int v, int q) {
+    const Geom& f = g->mg_geom[0];
+    double* b = kry_base(g) + 5 * (1 + (int64_t)g->mgp.krylov) * mg_stride(f) + (int64_t)v * mg_res_doubles(f);
+    return reinterpret_cast<float*>(b) + (int64_t)q * (box_of(f) + 64);
+}
+double* kry_part(pt_grid* g) {
+    const Geom& f = g->mg_geom[0];
+    const int64_t m = g->mgp.krylov;
+    return kry_base(g) + 5 * (1 + m) * mg_stride(f) + (1 + m) * mg_res_doubles(f);
+}
 double* mg_box(pt_grid* g, int l, int b) {
     double* base = g->gws + mg_res_doubles(g->mg_geom[0]) + mg_part_doubles(g->mg_geom, g->mg_levels);
     for (int k = 1; k < l; ++k) base += MG_NB * mg_stride(g->mg_geom[k]) + mg_res_doubles(g->mg_geom[k]);
@@ -1523,6 +1552,134 @@ pt_status mg_rho(pt_grid* g, double* r) {
     return PT_OK;
 }
 
+// The Krylov vectors of the fine grid with its present copies.
+KryVecs kry_vecs(pt_grid* g) {
+    KryVecs v{};
+    const int fl[5] = {PT_VX, PT_VY, PT_VZ, PT_PT, PT_PF};
+    for (int q = 0; q < 5; ++q) {
+        v.rk[q] = mg_res(g, 0, q);
+        v.ry[q] = kry_vec(g, 0, q);
+        v.x[q] = kry_x(g, q);
+        v.y[q] = cur(g, fl[q]);
+    }
+    // the stopping norm's scales: momentum rows by the velocity reference,
+    // pressure rows by the pressure reference (the other one if one is 0)
+    const double rv = g->ref_v > 0.0 ? g->ref_v : (g->ref_p > 0.0 ? g->ref_p : 1.0);
+    const double rp = g->ref_p > 0.0 ? g->ref_p : rv;
+    v.wv2 = 1.0 / (rv * rv);
+    v.wp2 = 1.0 / (rp * rp);
+    return v;
+}
+
+// The first n totals of the last reduction (synchronises).
+pt_status kry_read(pt_grid* g, double* out, int n) {
+    hipError_t e = hipMemcpyAsync(out, kry_part(g) + (int64_t)KRY_BLOCKS * KRY_SLOTS, n * sizeof(double),
+                                  hipMemcpyDeviceToHost, g->stream);
+    const hipError_t es = hipStreamSynchronize(g->stream);
+    if (e == hipSuccess) e = es;
+    if (e != hipSuccess) return hip_fail(g, e, "Krylov sums copy");
+    for (int k = 0; k < n; ++k)
+        if (!std::isfinite(out[k])) return fail(g, PT_EDIVERGED, "non-finite Krylov inner product");
+    return PT_OK;
+}
+
+// Krylov acceleration of the cycle (pt_solve_mg with krylov > 0): the
+// recombination of multigrid iterates over earlier corrections known as
+// Krylov subspace acceleration.  The fine residual boxes hold r(x) of the
+// iterate x; the cycle's result y is formed in the fine fields from x, its
+// residual goes to the Krylov residual boxes.  The step keeps the whole
+// cycle, x' = y + sum gamma_s p_s, with gamma minimising
+// |r(y) - sum gamma_s A p_s|_W over the stored directions (W-orthogonal
+// images, so one inner product each); the cycle's own step z = y - x,
+// made W-orthogonal to the directions that stay, is stored for the
+// following steps.  Minimising along z as well (GCR) stagnates: single
+// cycles raise the residual norm transiently on the stage systems, where
+// the minimiser then takes no step at all; so z is never scaled down.
+pt_status solve_mg_krylov(pt_grid* g, double rtol, int64_t max_cycles, int64_t* cycles, double* rho) {
+    const int m = g->mgp.krylov;
+    const Geom& f = g->mg_geom[0];
+    double app[KRY_MAX] = {};   // <A p_s, A p_s>_W of the stored slots
+    int nd = 0, head = 0;       // slots in use; the oldest once all are
+    int64_t c = 0;
+    double r = INFINITY;
+    pt_status st = mg_smooth(g, 0, g->mgp.nu1);
+    if (st == PT_OK) st = mg_residual(g, 0);
+    if (st == PT_OK) st = mg_rho(g, &r);
+    bool saved = false;
+    while (st == PT_OK && !(r <= rtol) && c < max_cycles) {
+        hipError_t e = hipSuccess;
+        if (!saved) {
+            e = launch_kry_save(f, kry_vecs(g), g->stream);
+            if (e != hipSuccess) return hip_fail(g, e, "Krylov save");
+            saved = true;
+        }
+        // y: one cycle from x
+        st = mg_correct(g, 0);
+        if (st == PT_OK) st = mg_smooth(g, 0, g->mgp.nu2 + g->mgp.nu1);
+        if (st != PT_OK) break;
+        {
+            SweepPtrs<double> p = mg_ptrs(g, 0);
+            p.res_fx = kry_vec(g, 0, 0); p.res_fy = kry_vec(g, 0, 1); p.res_fz = kry_vec(g, 0, 2);
+            p.res_rpt = kry_vec(g, 0, 3); p.res_rpf = kry_vec(g, 0, 4);
+            e = launch_iteration(f, g->coef, p, MD_RESID, 1, g->stream);
+            if (e != hipSuccess) return hip_fail(g, e, "multigrid residual");
+        }
+        st = reduce_norms(g);
+        double ry = INFINITY;
+        if (st == PT_OK) st = mg_rho(g, &ry);
+        if (st != PT_OK) break;
+        ++c;
+        if (ry <= rtol) {   // y meets the tolerance: keep it
+            r = ry;
+            break;
+        }
+        // the new direction replaces the oldest once all slots are in use
+        const int slot = nd < m ? nd : head;
+        KryVecs v = kry_vecs(g);
+        v.na = nd;
+        for (int s = 0; s < nd; ++s)
+            for (int q = 0; q < 5; ++q) {
+                v.p[s][q] = kry_p(g, s, q);
+                v.ap[s][q] = kry_vec(g, 1 + s, q);
+            }
+        for (int q = 0; q < 5; ++q) {
+            v.p_new[q] = kry_p(g, slot, q);
+            v.ap_new[q] = kry_vec(g, 1 + slot, q);
+        }
+        if (nd > 0) {
+            e = launch_kry_dots(f, v, kry_part(g), g->stream);
+            if (e != hipSuccess) return hip_fail(g, e, "Krylov inner products");
+            double d[KRY_SLOTS];
+            st = kry_read(g, d, KRY_SLOTS);
+            if (st != PT_OK) break;
+            for (int s = 0; s < nd; ++s) {
+                // r(y + gamma p_s) = r(y) - gamma A p_s
+                v.gamma[s] = d[KRY_MAX + s] / app[s];
+                v.beta[s] = s == slot ? 0.0 : (d[s] - d[KRY_MAX + s]) / app[s];
+            }
+        }
+        e = launch_kry_update(f, v, kry_part(g), g->stream);
+        if (e != hipSuccess) return hip_fail(g, e, "Krylov step");
+        double t[1];
+        st = kry_read(g, t, 1);
+        if (st != PT_OK) break;
+        if (t[0] > 0.0) {
+            app[slot] = t[0];
+            if (nd < m) ++nd; else head = (head + 1) % m;
+        } else {
+            // z lies in the span of the stored directions: start afresh
+            nd = 0;
+            head = 0;
+        }
+        st = mg_residual(g, 0);
+        if (st == PT_OK) st = mg_rho(g, &r);
+    }
+    if (cycles) *cycles = c;
+    if (rho) *rho = r;
+    if (st != PT_OK) return st;
+    return (r <= rtol) ? PT_OK : PT_ENOTCONV;
+}
+
 pt_status solve_mg_core(pt_grid* g, double rtol, int64_t max_cycles, int64_t* cycles, double* rho) {
     pt_status st = check_ready(g);
     if (st != PT_OK) return st;
@@ -1543,6 +1700,7 @@ pt_status solve_mg_core(pt_grid* g, double rtol, int64_t max_cycles, int64_t* cy
         if (st == PT_OK) st = mg_rho(g, &r);
         if (st != PT_OK) return st;
     }
+    if (g->mgp.krylov > 0) return solve_mg_krylov(g, rtol, max_cycles, cycles, rho);
     int64_t c = 0;
     for (;;) {
         st = mg_smooth(g, 0, g->mgp.nu1);

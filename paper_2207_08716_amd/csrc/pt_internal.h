@@ -270,6 +270,37 @@ hipError_t launch_mg_restrict_fold(const Geom& gf, const Geom& gc, const float* 
 hipError_t launch_mg_prolong_add(const Geom& gf, const Geom& gc, int kind, const double* src, double* dst,
                                  hipStream_t s);
 
+// Krylov acceleration of the multigrid cycle (krylov_kernels.hip): the
+// cycles' iterates recombined over a subspace of their own steps.
+// Vectors are the fine grid's five unknowns or five residuals in their
+// padded boxes; only entries that carry an equation are read or written.
+constexpr int KRY_MAX = 8;         // stored directions at most
+constexpr int KRY_SLOTS = 16;      // partial sums per block (>= 2 KRY_MAX)
+constexpr int KRY_BLOCKS = 2048;   // blocks of the reduction kernels at most
+struct KryVecs {
+    const float* rk[5];            // residual of the iterate x_k
+    const float* ry[5];            // residual of the cycle's result y
+    double* x[5];                  // saved x_k (boxes of the fine geometry)
+    double* y[5];                  // the fine fields' present copies
+    const double* p[KRY_MAX][5];   // stored directions p_s and images A p_s, s < na
+    const float* ap[KRY_MAX][5];
+    double* p_new[5];              // the new direction and its image
+    float* ap_new[5];
+    double gamma[KRY_MAX];         // x' = y + sum gamma_s p_s
+    double beta[KRY_MAX];          // p = (y - x) - sum beta_s p_s
+    double wv2, wp2;               // squared weights of momentum and pressure rows
+    int na;
+};
+// Partial sums go to part[0 .. KRY_BLOCKS * KRY_SLOTS), their totals to the
+// KRY_SLOTS doubles after them.
+// dots: totals s = <r_k, A p_s>_W, KRY_MAX + s = <r_y, A p_s>_W, s < na.
+hipError_t launch_kry_dots(const Geom& g, const KryVecs& v, double* part, hipStream_t s);
+// update: x, y <- y + sum gamma_s p_s; p_new = y - x - sum beta_s p_s,
+// ap_new = r_k - r_y - sum beta_s A p_s; total 0 = <ap_new, ap_new>_W.
+hipError_t launch_kry_update(const Geom& g, const KryVecs& v, double* part, hipStream_t s);
+// save: x <- y.
+hipError_t launch_kry_save(const Geom& g, const KryVecs& v, hipStream_t s);
+
 // Adjoint of a Picard run (adjoint_kernels.hip).  rhs holds -xbar, the
 // right-hand side of the transposed stage solve in the slots of the
 // correction sweep (momentum rows on the faces, r_Pt and r_Pf in the cells).
