@@ -35,6 +35,8 @@ METRIC = "PT-iter T_eff GB/s (% HBM peak) at 511³; mixed vs FP64 time-to-tol 1e
 # stage systems measured (4 and 2 stall on some of them; the memory is
 # 5 (m + 1) FP64 and FP32 fine boxes)
 MG_KRYLOV = 8
+# V-cycles per stage of the porosity-wave run
+WAVES_MAX_CYCLES = 1500
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_iter_thesis_511.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2207_08716_amd", "csrc", "iter_kernel.hip")
@@ -322,25 +324,34 @@ def waves_run(n: int, steps: int, rtol: float = 1e-8, stages: int = 5):
     solved by multigrid to rtol: the wave front after every step and the
     time per step."""
     import torch
-    from paper_2207_08716_amd import inputs, schedules
+    from paper_2207_08716_amd import abi, inputs, schedules
     cfg = inputs.config_waves(n)
     g = schedules.make_grid(cfg, inputs.initial_fields(cfg))
     # this box is 30 compaction lengths wide: grids coarser than ~2 per cell
     # break the damped PT of the coarsest grid and the smoother needs the
-    # smaller velocity step (prototyped on the oracle): stop at 16-31 cells
+    # smaller velocity step (prototyped on the oracle): stop at 16-31 cells;
+    # 8 + 8 smoothing sweeps and the Krylov acceleration carry the run past
+    # the decompacting layer under the top wall (4 + 4: divergence at the
+    # 15th step at 127^3)
     levels, m = 1, n
     while (m + 1) // 2 >= 16:
         m = (m + 1) // 2
         levels += 1
-    mg = dict(levels=levels, c_v=16.0, coarse_sweeps=400, krylov=MG_KRYLOV)
+    mg = dict(levels=levels, c_v=16.0, coarse_sweeps=400, nu1=8, nu2=8, krylov=MG_KRYLOV)
     g.enable_mg(**mg)
     fronts = [z_front(g, cfg.phys.phi0)]
     cycles, times = [], []
     ok_all = True
+    diverged = None
     for s in range(steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        cyc, rho, ok = g.picard_step(s >= 1, stages, rtol, max_iter=400, solver="mg")
+        try:
+            cyc, rho, ok = g.picard_step(s >= 1, stages, rtol, max_iter=WAVES_MAX_CYCLES, solver="mg")
+        except abi.PTError as e:
+            print(f"porosity waves n={n} step {s + 1}: {e}", file=sys.stderr, flush=True)
+            diverged = s + 1
+            break
         torch.cuda.synchronize()
         times.append(round(time.perf_counter() - t0, 3))
         cycles.append(cyc)
@@ -353,7 +364,8 @@ def waves_run(n: int, steps: int, rtol: float = 1e-8, stages: int = 5):
     torch.cuda.empty_cache()
     return {"n": n, "workload": f"{n}^3 porosity-wave box (L = 30, three sources of width 1, DP cap, R0 = 100), "
                                 f"dt = {cfg.phys.dt}", "steps": steps, "picard_stages": stages, "rtol": rtol,
-            "solver": "multigrid", "mg": mg, "converged": ok_all, "v_cycles": cycles, "step_s": times,
+            "solver": "multigrid", "mg": mg, "converged": ok_all and diverged is None, "diverged_at_step": diverged,
+            "v_cycles": cycles, "step_s": times,
             "z_front": fronts, "cell_size": cfg.phys.lz / n}
 
 

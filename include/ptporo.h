@@ -358,9 +358,10 @@ pt_status pt_picard_step(pt_grid* g, int32_t update_history, int32_t n_picard, d
  * rho_i h^2 / (c_v mu_s), mu_s / n_pt and h^2 (1 + beta_d B/alpha) /
  * (c_pf k_loc).  Coarsest grid: coarse_sweeps damped PT sweeps with the
  * handle's parameters.  Coarse operators: the same discretisation with
- * k/mu_f averaged harmonically and eta_phi, mu_s, ln(1-phi) arithmetically
- * over the finer grid; the coarse right-hand side sits in the coarse
- * grid's Fo and old-pressure fields.  Needs beta_d > 0 and alpha B != 1. */
+ * k/mu_f averaged harmonically, eta_phi by eta_mean and mu_s, ln(1-phi)
+ * arithmetically over the finer grid; the coarse right-hand side sits in
+ * the coarse grid's Fo and old-pressure fields.  Needs beta_d > 0 and
+ * alpha B != 1. */
 #define PT_MG_MAX_LEVELS 12
 typedef struct {
     int32_t version;          /* PT_ABI_VERSION                                      */
@@ -372,7 +373,8 @@ typedef struct {
     double c_v, c_pf;         /* the smoother's pseudo-step factors                  */
     int32_t krylov;           /* 0: plain cycles; 1..PT_MG_MAX_KRYLOV: Krylov
                                  acceleration keeping that many directions         */
-    int32_t reserved;         /* 0                                                   */
+    int32_t eta_mean;         /* eta_phi averaged down the hierarchy: 0 arithmetic,
+                                 1 harmonic, 2 geometric mean                      */
 } pt_mg_params;
 #define PT_MG_MAX_KRYLOV 8
 

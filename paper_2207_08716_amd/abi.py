@@ -73,18 +73,22 @@ MG_MAX_KRYLOV = 8
 class MgParams(C.Structure):
     _fields_ = [("version", C.c_int32), ("levels", C.c_int32), ("nu1", C.c_int32), ("nu2", C.c_int32),
                 ("coarse_sweeps", C.c_int32), ("n_pt", C.c_int32), ("c_v", C.c_double), ("c_pf", C.c_double),
-                ("krylov", C.c_int32), ("reserved", C.c_int32)]
+                ("krylov", C.c_int32), ("eta_mean", C.c_int32)]
 
 
-def mg_params(levels=0, nu1=4, nu2=4, coarse_sweeps=50, n_pt=4, c_v=8.0, c_pf=6.1, krylov=0) -> MgParams:
+def mg_params(levels=0, nu1=4, nu2=4, coarse_sweeps=50, n_pt=4, c_v=8.0, c_pf=6.1, krylov=0,
+              eta_mean=2) -> MgParams:
     """Multigrid parameters (pt_mg_params).  Defaults, measured on the mixed
     workload at 511^3 (a Picard step of 5 stages to 1e-8): the smoother
     diverges at c_v = 5 and at n_pt = 2, so c_v = 8 keeps a margin (80
     V-cycles, 6.55 s, against 77 and 6.32 s at c_v = 6.1); n_pt = 6 would
     cost 5-25 % more cycles.  krylov = m > 0: Krylov acceleration of the
-    cycles with m stored directions."""
+    cycles with m stored directions.  eta_mean: the geometric mean of eta_phi
+    on coarse grids (the same cycle counts as the arithmetic one on the unit
+    cube, 15 % fewer on the production box, and the porosity-wave run at
+    127^3 lasts 13 converged steps instead of 7; harmonic means diverge)."""
     return MgParams(ABI_VERSION, int(levels), int(nu1), int(nu2), int(coarse_sweeps), int(n_pt),
-                    float(c_v), float(c_pf), int(krylov), 0)
+                    float(c_v), float(c_pf), int(krylov), int(eta_mean))
 
 
 # Reactive porosity waves (include/ptwaves.h).

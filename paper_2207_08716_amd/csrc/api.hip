@@ -1245,8 +1245,8 @@ namespace {
 // grid's constant terms: the face fields Fo (momentum) and the old pressures
 // (whose terms in r_Pt and r_Pf are linear), with the physical constants
 // (buoyancy, background shear) set to zero so that the residual at e = 0 is
-// exactly R r.  Coefficients (k/mu_f harmonically, eta_phi, mu_s and
-// ln(1-phi) arithmetically) are averaged down at each solve.
+// exactly R r.  Coefficients (k/mu_f harmonically, eta_phi by the chosen
+// mean, mu_s and ln(1-phi) arithmetically) are averaged down at each solve.
 //
 // Workspace (doubles, boxes a box plus 256 bytes apart): the fine grid's FP32
 // residual (5 boxes); per-block maxima of the coarse residual sweeps (sized
@@ -1279,7 +1279,7 @@ bool mg_valid(const pt_mg_params* m) {
     if (m->nu1 < 1 || m->nu2 < 0 || m->nu1 > 1000 || m->nu2 > 1000) return false;
     if (m->coarse_sweeps < 1 || m->coarse_sweeps > 1000000 || m->n_pt < 1) return false;
     if (!(m->c_v > 0.0 && std::isfinite(m->c_v)) || !(m->c_pf > 0.0 && std::isfinite(m->c_pf))) return false;
-    if (m->krylov < 0 || m->krylov > PT_MG_MAX_KRYLOV || m->reserved != 0) return false;
+    if (m->krylov < 0 || m->krylov > PT_MG_MAX_KRYLOV || m->eta_mean < 0 || m->eta_mean > 2) return false;
     return true;
 }
 
@@ -1527,7 +1527,7 @@ pt_status mg_coefficients(pt_grid* g) {
         const double* mus = l == 1 ? cur(g, PT_MUS) : mg_box(g, l - 1, MG_MUS);
         const double* lp = l == 1 ? cur(g, PT_LP) : mg_box(g, l - 1, MG_LP);
         e = launch_mg_restrict(gf, gc, 0, kc, mg_box(g, l, MG_KC), 1, g->stream);
-        if (e == hipSuccess) e = launch_mg_restrict(gf, gc, 0, eta, mg_box(g, l, MG_ETA), 0, g->stream);
+        if (e == hipSuccess) e = launch_mg_restrict(gf, gc, 0, eta, mg_box(g, l, MG_ETA), g->mgp.eta_mean, g->stream);
         if (e == hipSuccess) e = launch_mg_restrict(gf, gc, 0, mus, mg_box(g, l, MG_MUS), 0, g->stream);
         if (e == hipSuccess) e = launch_mg_restrict(gf, gc, 0, lp, mg_box(g, l, MG_LP), 0, g->stream);
     }

@@ -95,7 +95,8 @@ struct Ext {
 __host__ __device__ inline Ext ext(const Geom& g) { return Ext{g.nx, g.ny, g.nz, g.P, g.S}; }
 
 // Restriction of one field of staggering (fx, fy, fz: face along that
-// axis).  mode 0: average, 1: harmonic average.  Walls' normal faces: 0.
+// axis).  mode 0: average, 1: harmonic average, 2: geometric average.
+// Walls' normal faces: 0.
 template <typename TS>
 __global__ __launch_bounds__(TB) void k_mg_restrict(Ext f, Ext c, bool fx, bool fy, bool fz, const TS* __restrict__ src,
                                                     double* __restrict__ dst, int mode) {
@@ -129,7 +130,7 @@ __global__ __launch_bounds__(TB) void k_mg_restrict(Ext f, Ext c, bool fx, bool 
                 for (int q = 0; q < MAXT; ++q) {
                     if (q < tx.n) {
                         const double v = (double)row[q];
-                        r += tx.w[q] * (mode ? 1.0 / v : v);
+                        r += tx.w[q] * (mode == 0 ? v : mode == 1 ? 1.0 / v : log(v));
                     }
                 }
                 s += wy * r;
@@ -137,7 +138,7 @@ __global__ __launch_bounds__(TB) void k_mg_restrict(Ext f, Ext c, bool fx, bool 
             }
         }
         ws *= tx.sum;
-        dst[o] = (ws > 0.0) ? (mode ? ws / s : s / ws) : 0.0;
+        dst[o] = (ws > 0.0) ? (mode == 0 ? s / ws : mode == 1 ? ws / s : exp(s / ws)) : 0.0;
     }
 }
 
@@ -217,12 +218,12 @@ unsigned blocks_for(int64_t n) { return (unsigned)std::min<int64_t>((n + TB - 1)
 
 }  // namespace
 
-hipError_t launch_mg_restrict(const Geom& gf, const Geom& gc, int kind, const double* src, double* dst, int harmonic,
+hipError_t launch_mg_restrict(const Geom& gf, const Geom& gc, int kind, const double* src, double* dst, int mean,
                               hipStream_t s) {
     const bool fx = kind == 1, fy = kind == 2, fz = kind == 3;
     const int64_t n = (int64_t)(gc.nx + fx) * (gc.ny + fy) * (gc.nz + fz);
     hipLaunchKernelGGL(k_mg_restrict<double>, dim3(blocks_for(n)), dim3(TB), 0, s, ext(gf), ext(gc), fx, fy, fz, src,
-                       dst, harmonic);
+                       dst, mean);
     return hipGetLastError();
 }
 

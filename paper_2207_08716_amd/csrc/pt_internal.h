@@ -257,9 +257,10 @@ hipError_t launch_apply_correction(const Geom& g, const MixedPtrs& m, hipStream_
 
 // Multigrid transfers between a fine grid gf and its coarse grid gc
 // (mg_kernels.hip).  kind: 0 cells, 1/2/3 faces normal to x/y/z.
-// Restriction: averages (harmonic != 0: harmonic averages) of the fine
-// values around each coarse point, zero on the walls' normal faces.
-hipError_t launch_mg_restrict(const Geom& gf, const Geom& gc, int kind, const double* src, double* dst, int harmonic,
+// Restriction: averages (mean 0: arithmetic, 1: harmonic, 2: geometric)
+// of the fine values around each coarse point, zero on the walls' normal
+// faces.
+hipError_t launch_mg_restrict(const Geom& gf, const Geom& gc, int kind, const double* src, double* dst, int mean,
                               hipStream_t s);
 hipError_t launch_mg_restrict32(const Geom& gf, const Geom& gc, int kind, const float* src, double* dst,
                                 hipStream_t s);

@@ -171,15 +171,14 @@ def test_multigrid_entry_points_validate_on_the_host(lib):
         assert lib.pt_mg_workspace_size(h, C.byref(abi.mg_params(levels=5)), C.byref(sz)) == -1
         for bad in (dict(levels=1), dict(levels=13), dict(nu1=0), dict(nu2=-1), dict(coarse_sweeps=0),
                     dict(n_pt=0), dict(c_v=0.0), dict(c_pf=float("nan")), dict(krylov=-1),
-                    dict(krylov=abi.MG_MAX_KRYLOV + 1)):
+                    dict(krylov=abi.MG_MAX_KRYLOV + 1), dict(eta_mean=3)):
             q = abi.mg_params(**bad)
             assert lib.pt_mg_workspace_size(h, C.byref(q), C.byref(sz)) == -1, bad
         q = abi.mg_params()
         q.version = 1
         assert lib.pt_mg_workspace_size(h, C.byref(q), C.byref(sz)) == -1
-        q = abi.mg_params()
-        q.reserved = 1
-        assert lib.pt_mg_workspace_size(h, C.byref(q), C.byref(sz)) == -1
+        for bad in (-1, 3):
+            assert lib.pt_mg_workspace_size(h, C.byref(abi.mg_params(eta_mean=bad)), C.byref(sz)) == -1
         # Krylov acceleration: 5 (m + 1) FP64 and 5 (m + 1) FP32 fine boxes more
         # (plus the skews between boxes and the partial sums of the inner products)
         box = 64 * 41 * 18
