@@ -383,7 +383,9 @@ typedef struct {
  * quarter of the fine grid's fields; with krylov = m, a further 5 (m + 1)
  * FP64 and 5 (m + 1) FP32 fine boxes): query, then bind a device buffer
  * (256-byte aligned) of at least that size; binding clears it (enqueued).
- * PT_EINVAL if the grid cannot be coarsened to the requested levels. */
+ * PT_EINVAL if the grid cannot be coarsened to the requested levels, and
+ * at binding with krylov > 0 if the row pitch is not a multiple of 4 (the
+ * Krylov kernels move 4 columns as one vector). */
 pt_status pt_mg_workspace_size(const pt_grid* g, const pt_mg_params* mg, size_t* bytes);
 pt_status pt_bind_mg_workspace(pt_grid* g, const pt_mg_params* mg, void* dev_ptr, size_t bytes);
 /* The bound hierarchy: levels (0 if none) and, if counts is not NULL, the

@@ -1736,6 +1736,8 @@ pt_status pt_bind_mg_workspace(pt_grid* g, const pt_mg_params* mg, void* dev_ptr
     if (!mg_valid(mg)) return fail(g, PT_EINVAL, "bad multigrid parameters");
     const size_t need = mg_needed(g, *mg);
     if (!need) return fail(g, PT_EINVAL, "grid too small to coarsen to the requested levels");
+    if (mg->krylov > 0 && g->geom.P % KRY_VW != 0)
+        return fail(g, PT_EINVAL, "Krylov acceleration needs a row pitch that is a multiple of 4");
     if (!dev_ptr || (reinterpret_cast<uintptr_t>(dev_ptr) & 255u) || bytes < need)
         return fail(g, PT_EINVAL, "multigrid workspace missing, unaligned or too small");
     g->mgp = *mg;

@@ -277,7 +277,8 @@ hipError_t launch_mg_prolong_add(const Geom& gf, const Geom& gc, int kind, const
 // padded boxes; only entries that carry an equation are read or written.
 constexpr int KRY_MAX = 8;         // stored directions at most
 constexpr int KRY_SLOTS = 16;      // partial sums per block (>= 2 KRY_MAX)
-constexpr int KRY_BLOCKS = 2048;   // blocks of the reduction kernels at most
+constexpr int KRY_BLOCKS = 2048;
+constexpr int KRY_VW = 4;          // columns per work item (the row pitch a multiple of it)   // blocks of the reduction kernels at most
 struct KryVecs {
     const float* rk[5];            // residual of the iterate x_k
     const float* ry[5];            // residual of the cycle's result y

@@ -189,6 +189,21 @@ def test_multigrid_entry_points_validate_on_the_host(lib):
             need = 5 * (m + 1) * box * 8 + 5 * (m + 1) * box * 4
             assert need <= extra <= need + (1 << 20), (m, extra, need)
         assert lib.pt_bind_mg_workspace(h, C.byref(good), C.c_void_p(0x1008), 1 << 40) == -1
+    finally:
+        lib.pt_destroy(h)
+    # the Krylov kernels move 4 columns as one vector: a pitch of 41 is refused
+    h = C.c_void_p()
+    assert lib.pt_create(40, 31, 31, 41, C.byref(p), C.byref(h)) == 0
+    try:
+        k8 = abi.mg_params(krylov=8)
+        assert lib.pt_mg_workspace_size(h, C.byref(k8), C.byref(sz)) == 0
+        assert lib.pt_bind_mg_workspace(h, C.byref(k8), C.c_void_p(0x1000), 1 << 40) == -1
+        assert b"multiple of 4" in lib.pt_last_error(h)
+    finally:
+        lib.pt_destroy(h)
+    h = C.c_void_p()
+    assert lib.pt_create(63, 40, 17, 64, C.byref(p), C.byref(h)) == 0
+    try:
         assert lib.pt_bind_mg_workspace(h, C.byref(good), C.c_void_p(0x1000), 8) == -1
         n = C.c_int32()
         assert lib.pt_mg_levels(h, C.byref(n), None) == 0 and n.value == 0
