@@ -199,3 +199,27 @@ def test_krylov_mg_porosity_wave_steps_match_pt_steps():
     # the porosity moved: the sources rose
     assert np.abs(out["mg"]["lp"] - np.log(1.0 - f["phi"])).max() > 1e-3
     assert max(worst.values()) <= 1e-6, worst
+
+
+def test_krylov_mg_resumes_after_the_cycle_cap():
+    """A call that stops at its cycle cap leaves a valid state (PT_ENOTCONV):
+    the next call starts without stored directions and reaches the same
+    stage solution; one stored direction (m = 1) converges as well."""
+    nx, ny, nz = 40, 30, 22
+    cfg = dataclasses.replace(inputs.config_mixed(nx), nx=nx, ny=ny, nz=nz)
+    g, o = _stage_pair(cfg, 1)
+    it_o, rho_o = o.solve_linear(1e-12, 4_000_000)
+    assert rho_o <= 1e-12
+    c1, r1, ok1 = g.solve_mg(1e-11, max_cycles=3, krylov=8)
+    assert not ok1 and c1 == 3 and 1e-11 < r1 < 10.0
+    c2, r2, ok2 = g.solve_mg(1e-11, max_cycles=200)
+    print(f"capped at 3: rho {r1:.2e}; resumed: {c2} cycles, rho {r2:.2e}", flush=True)
+    assert ok2
+    worst = {k: _rel(g.get(k), o.f[k]) for k in FIELDS}
+    assert max(worst.values()) <= 1e-8, worst
+    g1, _ = _stage_pair(cfg, 1)
+    c, r, ok = g1.solve_mg(1e-11, max_cycles=200, krylov=1)
+    print(f"m = 1: {c} cycles, rho {r:.2e}", flush=True)
+    assert ok
+    worst = {k: _rel(g1.get(k), o.f[k]) for k in FIELDS}
+    assert max(worst.values()) <= 1e-8, worst
