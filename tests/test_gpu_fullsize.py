@@ -1,8 +1,9 @@
 """Full-size checks in the launch configurations the benchmark times: the
 GPU's refresh + 3 thesis-schedule iterations against the oracle run on
 windows around sampled points (corners, tile and z-chunk seams, interior),
-at 511^3 (the anomaly workload) and on the 511 x 511 x 1022 production box
-of Table 2 (background shear, power law, decompaction weakening 2000); see
+at 511^3 (the anomaly workload), on the 511 x 511 x 1022 production box
+of Table 2 (background shear, power law, decompaction weakening 2000) and
+on the 767^3 porosity-wave domain; see
 window_oracle.py for why a window reproduces the full-grid value.  The
 background shear enters as a uniform strain rate and the anomaly is cut
 from the full grid's porosity, so the windows hold there too."""
@@ -65,12 +66,16 @@ def _box_points(counts, rng, count):
     return sorted(pts)
 
 
-def test_fullsize_production_box_sampled_against_windowed_oracle():
+@pytest.mark.parametrize("workload", ["production_511x511x1022", "waves_767"])
+def test_fullsize_boxes_sampled_against_windowed_oracle(workload):
+    """The production box of Table 2 at 511 x 511 x 1022 and the porosity-wave
+    domain (three sources, DP cap, R0 = 100) at 767^3, the other two
+    workloads the benchmark times under the thesis schedule."""
     import torch
     from paper_2207_08716_amd import schedules
     m = 3
-    cfg = inputs.config_production(511, 511, 1022)
-    print("production box 511 x 511 x 1022: set-up", flush=True)
+    cfg = inputs.config_production(511, 511, 1022) if workload.startswith("production") else inputs.config_waves(767)
+    print(f"{workload}: set-up", flush=True)
     f = inputs.initial_fields(cfg)
     g = schedules.make_grid(cfg, f)
     g.begin_step(False)
@@ -84,17 +89,22 @@ def test_fullsize_production_box_sampled_against_windowed_oracle():
     g.close()
     del g
     torch.cuda.empty_cache()
-    print("production box: windows", flush=True)
+    print(f"{workload}: windows", flush=True)
     ref = {name: np.zeros(len(pts)) for name in got}
     for q, p in enumerate(pts):
         w = window_values(cfg, f["phi"], f["k0"], p, 2 * m + 4, m)
         for name in got:
             ref[name][q] = w[name]
+    # the components of V (and of R) share one scale, the largest sampled
+    # component: away from the sources a horizontal component can be 1e-9 of
+    # the vertical one after 3 iterations, its digits then being round-off
+    # of the larger terms
+    vec = {"v": ("vx", "vy", "vz"), "r": ("rx", "ry", "rz")}
     worst = {}
     for name in got:
-        scale = np.abs(ref[name]).max()
+        group = vec.get(name[0]) if name in FACE_FIELDS else None
+        scale = max(np.abs(ref[c]).max() for c in group) if group else np.abs(ref[name]).max()
         worst[name] = float(np.abs(got[name] - ref[name]).max() / scale) if scale > 0 else 0.0
     print(worst, flush=True)
     assert all(v <= 1e-12 for v in worst.values()), worst
-    # the background shear drives the velocities from the first iteration
-    assert np.abs(ref["vx"]).max() > 0 and np.abs(ref["pf"]).max() > 0
+    assert np.abs(ref["vz"]).max() > 0 and np.abs(ref["pf"]).max() > 0
