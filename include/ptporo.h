@@ -378,7 +378,8 @@ typedef struct {
 } pt_mg_params;
 #define PT_MG_MAX_KRYLOV 8
 
-/* Workspace of a hierarchy (the fine grid's FP32 residual, and per coarse
+/* Workspace of a hierarchy (the fine grid's FP32 residual, the
+ * restriction's scratch of less than one fine FP64 box, and per coarse
  * grid 25 FP64 boxes plus, above the coarsest, 5 FP32 boxes: about a
  * quarter of the fine grid's fields; with krylov = m, a further 5 (m + 1)
  * FP64 and 5 (m + 1) FP32 fine boxes): query, then bind a device buffer

@@ -1253,7 +1253,7 @@ namespace {
 // for the first coarse grid, plus a flag slot); per coarse grid l: 25 FP64
 // boxes (the 8 iterated fields in two copies, ln(1-phi), Fo, the old
 // pressures, k/mu_f, eta_phi, mu_s) and, above the coarsest grid, its FP32
-// residual (5 boxes).
+// residual (5 boxes); the restriction's scratch (less than one fine FP64 box).
 constexpr int MG_NB = 25;
 constexpr int MG_LP = 16, MG_FOX = 17, MG_PTO = 20, MG_PFO = 21, MG_KC = 22, MG_ETA = 23, MG_MUS = 24;
 
@@ -1308,14 +1308,34 @@ int64_t mg_part_blocks(const Geom* geo, int L) {
 }
 int64_t mg_part_doubles(const Geom* geo, int L) { return (mg_part_blocks(geo, L) * NNORM + NNORM + 1 + 31) / 32 * 32; }
 
-// Doubles of the hierarchy's pieces (without the Krylov vectors).
-int64_t mg_core_doubles(const Geom* geo, int L) {
+// Doubles of the grids' pieces.
+int64_t mg_levels_doubles(const Geom* geo, int L) {
     int64_t n = mg_res_doubles(geo[0]) + mg_part_doubles(geo, L);
     for (int l = 1; l < L; ++l) {
         n += MG_NB * mg_stride(geo[l]);
         if (l < L - 1) n += mg_res_doubles(geo[l]);
     }
     return n;
+}
+
+// Scratch of the separable restriction, sized for the fine grid's (the
+// largest): the x-restricted field and the x- and y-restricted field.
+int64_t mg_scr_a(const Geom* geo) { return ((int64_t)(geo[0].nz + 1) * (geo[0].ny + 1) * geo[1].P + 31) / 32 * 32; }
+int64_t mg_scr_b(const Geom* geo) { return ((int64_t)(geo[0].nz + 1) * (geo[1].ny + 1) * geo[1].P + 31) / 32 * 32; }
+
+// The restriction rows of every grid transfer l -> l + 1: per axis, the rows
+// for cells and for faces normal to it.
+int64_t mg_tab_rows(const Geom& c, int axis) { return (axis == 0 ? c.nx : axis == 1 ? c.ny : c.nz) + 1; }
+int64_t mg_tab_doubles(const Geom* geo, int L) {
+    int64_t n = 0;
+    for (int l = 1; l < L; ++l)
+        for (int a = 0; a < 3; ++a) n += 2 * mg_tab_rows(geo[l], a) * MG_TAB;
+    return (n + 31) / 32 * 32;
+}
+
+// Doubles of the hierarchy's pieces (without the Krylov vectors).
+int64_t mg_core_doubles(const Geom* geo, int L) {
+    return mg_levels_doubles(geo, L) + mg_scr_a(geo) + mg_scr_b(geo) + mg_tab_doubles(geo, L);
 }
 
 // Krylov vectors after them: the saved iterate and m directions p (5 FP64
@@ -1346,6 +1366,19 @@ float* mg_res(pt_grid* g, int l, int q) {
     return reinterpret_cast<float*>(base) + (int64_t)q * (box_of(g->mg_geom[l]) + 64);
 }
 double* mg_partials(pt_grid* g) { return g->gws + mg_res_doubles(g->mg_geom[0]); }
+double* mg_scr(pt_grid* g, int b) {
+    double* base = g->gws + mg_levels_doubles(g->mg_geom, g->mg_levels);
+    return b == 0 ? base : base + mg_scr_a(g->mg_geom);
+}
+// Rows of the transfer from grid l to l + 1 along `axis` (face: for faces
+// normal to it).
+double* mg_tab(pt_grid* g, int l, int axis, int face) {
+    double* p = mg_scr(g, 1) + mg_scr_b(g->mg_geom);
+    for (int k = 1; k <= l; ++k)
+        for (int a = 0; a < 3; ++a) p += 2 * mg_tab_rows(g->mg_geom[k], a) * MG_TAB;
+    for (int a = 0; a < axis; ++a) p += 2 * mg_tab_rows(g->mg_geom[l + 1], a) * MG_TAB;
+    return p + (face ? mg_tab_rows(g->mg_geom[l + 1], axis) * MG_TAB : 0);
+}
 double* kry_base(pt_grid* g) { return g->gws + mg_core_doubles(g->mg_geom, g->mg_levels); }
 double* kry_x(pt_grid* g, int q) { return kry_base(g) + (int64_t)q * mg_stride(g->mg_geom[0]); }
 double* kry_p(pt_grid* g, int s, int q) { return kry_base(g) + (5 + 5 * (int64_t)s + q) * mg_stride(g->mg_geom[0]); }
@@ -1478,16 +1511,20 @@ pt_status mg_correct(pt_grid* g, int l) {
     const int cp = g->mg_cur[c] ? 8 : 0;
     for (int b = 0; b < 8 && e == hipSuccess; ++b) e = launch_fill(mg_box(g, c, cp + b), 0.0, nbox, g->stream);
     // right-hand side: the restricted residual in the constant terms
-    for (int a = 0; a < 3 && e == hipSuccess; ++a)
-        e = launch_mg_restrict32(gf, gc, a + 1, mg_res(g, l, a), mg_box(g, c, MG_FOX + a), g->stream);
+    for (int a = 0; a < 3 && e == hipSuccess; ++a) {
+        const double* tab[3] = {mg_tab(g, l, 0, a == 0), mg_tab(g, l, 1, a == 1), mg_tab(g, l, 2, a == 2)};
+        e = launch_mg_restrict32(gf, gc, a + 1, mg_res(g, l, a), mg_box(g, c, MG_FOX + a), mg_scr(g, 0), mg_scr(g, 1),
+                                 tab, g->stream);
+    }
     if (e == hipSuccess) {
         const pt_params& p = g->prm;
         // c(-pto + alpha pfo) = a, c(alpha pto - (alpha/B) pfo) = b, c = beta_d/dt
         const double k = p.beta_d / p.dt, al = p.alpha, ab = p.alpha / p.B;
         const double det = k * k * (ab - al * al);
         const double m[4] = {-k * ab / det, -k * al / det, -k * al / det, -k / det};
+        const double* tab[3] = {mg_tab(g, l, 0, 0), mg_tab(g, l, 1, 0), mg_tab(g, l, 2, 0)};
         e = launch_mg_restrict_fold(gf, gc, mg_res(g, l, 3), mg_res(g, l, 4), mg_box(g, c, MG_PTO),
-                                    mg_box(g, c, MG_PFO), m, g->stream);
+                                    mg_box(g, c, MG_PFO), m, mg_scr(g, 0), mg_scr(g, 1), tab, g->stream);
     }
     if (e != hipSuccess) return hip_fail(g, e, "multigrid restriction");
     pt_status st;
@@ -1748,6 +1785,15 @@ pt_status pt_bind_mg_workspace(pt_grid* g, const pt_mg_params* mg, void* dev_ptr
     // the walls' normal faces of the coarse corrections are never written:
     // clear the whole workspace once
     hipError_t e = launch_fill(g->gws, 0.0, (int64_t)(need / sizeof(double)), g->stream);
+    // the restriction rows of every transfer, once per hierarchy
+    for (int l = 0; l + 1 < g->mg_levels && e == hipSuccess; ++l) {
+        const Geom& f = g->mg_geom[l];
+        const Geom& c = g->mg_geom[l + 1];
+        const int nf[3] = {f.nx, f.ny, f.nz}, nc[3] = {c.nx, c.ny, c.nz};
+        for (int a = 0; a < 3 && e == hipSuccess; ++a)
+            for (int face = 0; face < 2 && e == hipSuccess; ++face)
+                e = launch_mg_taps(mg_tab(g, l, a, face), nf[a], nc[a], face, g->stream);
+    }
     if (e != hipSuccess) return hip_fail(g, e, "multigrid workspace clear");
     return PT_OK;
 }

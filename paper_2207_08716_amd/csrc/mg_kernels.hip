@@ -65,6 +65,7 @@ __device__ __forceinline__ void prange(int J, int nf, int nc, bool face, int& lo
 // P's entries for coarse index I (a coarse grid has ceil(n/2) cells, so the
 // ratio is at most 2 and the candidate range spans at most 7 fine points).
 constexpr int MAXT = 8;
+static_assert(MG_TAB == 2 + MAXT, "a restriction row holds its first index, its count and MAXT weights");
 struct Taps {
     int lo, n;
     double w[MAXT];
@@ -142,46 +143,67 @@ __global__ __launch_bounds__(TB) void k_mg_restrict(Ext f, Ext c, bool fx, bool 
     }
 }
 
-// Restricted pressure residuals (a, b) folded into old-pressure fields:
-// pto = m00 a + m01 b, pfo = m10 a + m11 b, the values whose terms in
-// r_Pt and r_Pf at the zero state are a and b.
-__global__ __launch_bounds__(TB) void k_mg_restrict_fold(Ext f, Ext c, const float* __restrict__ rpt,
-                                                         const float* __restrict__ rpf, double* __restrict__ pto,
-                                                         double* __restrict__ pfo, double m00, double m01,
-                                                         double m10, double m11) {
+// One axis of the separable restriction.  The restriction is a tensor
+// product of one-dimensional rows, each normalised to weight sum 1, so it
+// runs as three passes (x, then y, then z), each reading its input once in
+// rows instead of gathering every coarse point's 3D neighbourhood.  dst
+// holds the points (i, j, k) < (ex, ey, ez) whose coordinate along `axis`
+// is coarse and whose other coordinates are src's; strides sP, sS (src) and
+// dP, dS (dst).  tab: the axis's normalised rows (MG_TAB doubles per coarse
+// index: first fine index, count, weights), built once per hierarchy.
+// Launched on a 3D grid of GX x GY blocks (x: i, y: j, z: k), so that no
+// thread divides its index.
+constexpr int GX = 64, GY = 4;
+
+template <typename TI>
+__global__ __launch_bounds__(GX * GY) void k_mg_r1(const TI* __restrict__ src, int64_t sP, int64_t sS,
+                                                  double* __restrict__ dst, int64_t dP, int64_t dS, int ex, int ey,
+                                                  int axis, const double* __restrict__ tab) {
+    const int i = blockIdx.x * GX + threadIdx.x, j = blockIdx.y * GY + threadIdx.y, k = blockIdx.z;
+    if (i < ex && j < ey) {
+        const int64_t step = axis == 0 ? 1 : (axis == 1 ? sP : sS);
+        const int J = axis == 0 ? i : (axis == 1 ? j : k);
+        const double* row = tab + (int64_t)J * MG_TAB;
+        const int lo = (int)row[0], cnt = (int)row[1];
+        const int64_t base = (axis == 0 ? (int64_t)k * sS + (int64_t)j * sP
+                                        : (axis == 1 ? (int64_t)k * sS + i : (int64_t)j * sP + i)) +
+                             (int64_t)lo * step;
+        double r = 0.0;
+#pragma unroll
+        for (int q = 0; q < MAXT; ++q)
+            if (q < cnt) r += row[2 + q] * (double)src[base + q * step];
+        dst[(int64_t)k * dS + (int64_t)j * dP + i] = r;
+    }
+}
+
+dim3 grid3(int ex, int ey, int ez) { return dim3((unsigned)((ex + GX - 1) / GX), (unsigned)((ey + GY - 1) / GY), (unsigned)ez); }
+
+// The normalised restriction rows of one axis (fine nf, coarse nc points;
+// face: the field sits on faces normal to it, whose wall faces carry no
+// equation: skipped as inputs, rows of weight 0 for the coarse walls).
+__global__ __launch_bounds__(TB) void k_mg_taps(double* __restrict__ tab, int nf, int nc, bool face) {
+    const int J = blockIdx.x * TB + threadIdx.x;
+    if (J > nc - 1 + face) return;
+    double* row = tab + (int64_t)J * MG_TAB;
+    Taps tt;
+    taps(J, nf, nc, face, face, tt);
+    const bool none = (face && (J == 0 || J == nc)) || !(tt.sum > 0.0);
+    row[0] = tt.lo;
+    row[1] = none ? 0 : tt.n;
+#pragma unroll
+    for (int q = 0; q < MAXT; ++q) row[2 + q] = none ? 0.0 : tt.w[q] / tt.sum;
+}
+
+// Restricted pressure residuals (a, b) folded into old-pressure fields in
+// place: pto = m00 a + m01 b, pfo = m10 a + m11 b, the values whose terms
+// in r_Pt and r_Pf at the zero state are a and b.
+__global__ __launch_bounds__(TB) void k_mg_fold(Ext c, double* __restrict__ pto, double* __restrict__ pfo,
+                                                double m00, double m01, double m10, double m11) {
     const int64_t n = (int64_t)c.nx * c.ny * c.nz;
     for (int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x; t < n; t += (int64_t)gridDim.x * TB) {
         const int I = (int)(t % c.nx), J = (int)((t / c.nx) % c.ny), K = (int)(t / ((int64_t)c.nx * c.ny));
-        Taps tx;
-        taps(I, f.nx, c.nx, false, false, tx);
-        int yl, yh, zl, zh;
-        prange(J, f.ny, c.ny, false, yl, yh);
-        prange(K, f.nz, c.nz, false, zl, zh);
-        double a = 0.0, b = 0.0, ws = 0.0;
-        for (int k = zl; k <= zh; ++k) {
-            const double wz = pweight(k, K, f.nz, c.nz, false);
-            if (wz == 0.0) continue;
-            for (int j = yl; j <= yh; ++j) {
-                const double wy = pweight(j, J, f.ny, c.ny, false) * wz;
-                if (wy == 0.0) continue;
-                const int64_t row = (int64_t)k * f.S + (int64_t)j * f.P + tx.lo;
-                double ra = 0.0, rb = 0.0;
-#pragma unroll
-                for (int q = 0; q < MAXT; ++q) {
-                    if (q < tx.n) {
-                        ra += tx.w[q] * (double)rpt[row + q];
-                        rb += tx.w[q] * (double)rpf[row + q];
-                    }
-                }
-                a += wy * ra;
-                b += wy * rb;
-                ws += wy;
-            }
-        }
-        ws *= tx.sum;
-        a /= ws;
-        b /= ws;
         const int64_t o = (int64_t)K * c.S + (int64_t)J * c.P + I;
+        const double a = pto[o], b = pfo[o];
         pto[o] = m00 * a + m01 * b;
         pfo[o] = m10 * a + m11 * b;
     }
@@ -189,13 +211,13 @@ __global__ __launch_bounds__(TB) void k_mg_restrict_fold(Ext f, Ext c, const flo
 
 // fine += P coarse for one field of staggering (fx, fy, fz); the walls'
 // normal faces keep their values.
-__global__ __launch_bounds__(TB) void k_mg_prolong_add(Ext f, Ext c, bool fx, bool fy, bool fz,
-                                                       const double* __restrict__ src, double* __restrict__ dst) {
-    const int ex = f.nx + fx, ey = f.ny + fy, ez = f.nz + fz;
-    const int64_t n = (int64_t)ex * ey * ez;
-    for (int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x; t < n; t += (int64_t)gridDim.x * TB) {
-        const int i = (int)(t % ex), j = (int)((t / ex) % ey), k = (int)(t / ((int64_t)ex * ey));
-        if ((fx && (i == 0 || i == f.nx)) || (fy && (j == 0 || j == f.ny)) || (fz && (k == 0 || k == f.nz))) continue;
+__global__ __launch_bounds__(GX * GY) void k_mg_prolong_add(Ext f, Ext c, bool fx, bool fy, bool fz,
+                                                            const double* __restrict__ src,
+                                                            double* __restrict__ dst) {
+    const int ex = f.nx + fx, ey = f.ny + fy;
+    const int i = blockIdx.x * GX + threadIdx.x, j = blockIdx.y * GY + threadIdx.y, k = blockIdx.z;
+    if (i < ex && j < ey) {
+        if ((fx && (i == 0 || i == f.nx)) || (fy && (j == 0 || j == f.ny)) || (fz && (k == 0 || k == f.nz))) return;
         int x0, y0, z0;
         double tx, ty, tz;
         pw(i, f.nx, c.nx, fx, x0, tx);
@@ -227,28 +249,53 @@ hipError_t launch_mg_restrict(const Geom& gf, const Geom& gc, int kind, const do
     return hipGetLastError();
 }
 
-hipError_t launch_mg_restrict32(const Geom& gf, const Geom& gc, int kind, const float* src, double* dst,
-                                hipStream_t s) {
+namespace {
+
+// The three passes of a separable restriction of an FP32 fine field
+// (scratch sa: (nz_f + 1) (ny_f + 1) P_c doubles, sb: (nz_f + 1) (ny_c + 1) P_c;
+// tab: the rows of the x, y, z axes for this field's staggering).
+hipError_t restrict_sep(const Geom& gf, const Geom& gc, int kind, const float* src, double* dst, double* sa,
+                        double* sb, const double* const tab[3], hipStream_t s) {
     const bool fx = kind == 1, fy = kind == 2, fz = kind == 3;
-    const int64_t n = (int64_t)(gc.nx + fx) * (gc.ny + fy) * (gc.nz + fz);
-    hipLaunchKernelGGL(k_mg_restrict<float>, dim3(blocks_for(n)), dim3(TB), 0, s, ext(gf), ext(gc), fx, fy, fz, src,
-                       dst, 0);
+    const int64_t aS = gc.P * (int64_t)(gf.ny + 1), bS = gc.P * (int64_t)(gc.ny + 1);
+    const dim3 blk(GX, GY);
+    hipLaunchKernelGGL(k_mg_r1<float>, grid3(gc.nx + fx, gf.ny + fy, gf.nz + fz), blk, 0, s, src, gf.P, gf.S, sa,
+                       gc.P, aS, gc.nx + fx, gf.ny + fy, 0, tab[0]);
+    hipLaunchKernelGGL(k_mg_r1<double>, grid3(gc.nx + fx, gc.ny + fy, gf.nz + fz), blk, 0, s, (const double*)sa,
+                       gc.P, aS, sb, gc.P, bS, gc.nx + fx, gc.ny + fy, 1, tab[1]);
+    hipLaunchKernelGGL(k_mg_r1<double>, grid3(gc.nx + fx, gc.ny + fy, gc.nz + fz), blk, 0, s, (const double*)sb,
+                       gc.P, bS, dst, gc.P, gc.S, gc.nx + fx, gc.ny + fy, 2, tab[2]);
     return hipGetLastError();
 }
 
+}  // namespace
+
+hipError_t launch_mg_taps(double* tab, int nf, int nc, int face, hipStream_t s) {
+    hipLaunchKernelGGL(k_mg_taps, dim3((unsigned)((nc + 1 + TB - 1) / TB)), dim3(TB), 0, s, tab, nf, nc, face != 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_mg_restrict32(const Geom& gf, const Geom& gc, int kind, const float* src, double* dst,
+                                double* sa, double* sb, const double* const tab[3], hipStream_t s) {
+    return restrict_sep(gf, gc, kind, src, dst, sa, sb, tab, s);
+}
+
 hipError_t launch_mg_restrict_fold(const Geom& gf, const Geom& gc, const float* rpt, const float* rpf, double* pto,
-                                   double* pfo, const double m[4], hipStream_t s) {
+                                   double* pfo, const double m[4], double* sa, double* sb, const double* const tab[3],
+                                   hipStream_t s) {
+    hipError_t e = restrict_sep(gf, gc, 0, rpt, pto, sa, sb, tab, s);
+    if (e == hipSuccess) e = restrict_sep(gf, gc, 0, rpf, pfo, sa, sb, tab, s);
+    if (e != hipSuccess) return e;
     const int64_t n = (int64_t)gc.nx * gc.ny * gc.nz;
-    hipLaunchKernelGGL(k_mg_restrict_fold, dim3(blocks_for(n)), dim3(TB), 0, s, ext(gf), ext(gc), rpt, rpf, pto, pfo,
-                       m[0], m[1], m[2], m[3]);
+    hipLaunchKernelGGL(k_mg_fold, dim3(blocks_for(n)), dim3(TB), 0, s, ext(gc), pto, pfo, m[0], m[1], m[2], m[3]);
     return hipGetLastError();
 }
 
 hipError_t launch_mg_prolong_add(const Geom& gf, const Geom& gc, int kind, const double* src, double* dst,
                                  hipStream_t s) {
     const bool fx = kind == 1, fy = kind == 2, fz = kind == 3;
-    const int64_t n = (int64_t)(gf.nx + fx) * (gf.ny + fy) * (gf.nz + fz);
-    hipLaunchKernelGGL(k_mg_prolong_add, dim3(blocks_for(n)), dim3(TB), 0, s, ext(gf), ext(gc), fx, fy, fz, src, dst);
+    hipLaunchKernelGGL(k_mg_prolong_add, grid3(gf.nx + fx, gf.ny + fy, gf.nz + fz), dim3(GX, GY), 0, s, ext(gf),
+                       ext(gc), fx, fy, fz, src, dst);
     return hipGetLastError();
 }
 

@@ -262,11 +262,20 @@ hipError_t launch_apply_correction(const Geom& g, const MixedPtrs& m, hipStream_
 // faces.
 hipError_t launch_mg_restrict(const Geom& gf, const Geom& gc, int kind, const double* src, double* dst, int mean,
                               hipStream_t s);
+// Normalised restriction rows of one axis (fine nf, coarse nc points; face:
+// faces normal to the axis): MG_TAB doubles per coarse index (first fine
+// index, count, MG_TAB - 2 weights), nc + face rows.
+constexpr int MG_TAB = 10;
+hipError_t launch_mg_taps(double* tab, int nf, int nc, int face, hipStream_t s);
+// An FP32 fine field restricted by three separable passes through scratch
+// sa ((nz_f + 1) (ny_f + 1) P_c doubles) and sb ((nz_f + 1) (ny_c + 1) P_c),
+// with the rows of the x, y and z axes for its staggering.
 hipError_t launch_mg_restrict32(const Geom& gf, const Geom& gc, int kind, const float* src, double* dst,
-                                hipStream_t s);
+                                double* sa, double* sb, const double* const tab[3], hipStream_t s);
 // Restricted r_Pt, r_Pf (a, b) -> pto = m[0] a + m[1] b, pfo = m[2] a + m[3] b.
 hipError_t launch_mg_restrict_fold(const Geom& gf, const Geom& gc, const float* rpt, const float* rpf, double* pto,
-                                   double* pfo, const double m[4], hipStream_t s);
+                                   double* pfo, const double m[4], double* sa, double* sb, const double* const tab[3],
+                                   hipStream_t s);
 // dst (fine) += interpolated src (coarse); the walls' normal faces are kept.
 hipError_t launch_mg_prolong_add(const Geom& gf, const Geom& gc, int kind, const double* src, double* dst,
                                  hipStream_t s);
