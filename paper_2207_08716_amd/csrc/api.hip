@@ -1563,10 +1563,13 @@ pt_status mg_coefficients(pt_grid* g) {
         const double* eta = l == 1 ? cur(g, PT_ETA) : mg_box(g, l - 1, MG_ETA);
         const double* mus = l == 1 ? cur(g, PT_MUS) : mg_box(g, l - 1, MG_MUS);
         const double* lp = l == 1 ? cur(g, PT_LP) : mg_box(g, l - 1, MG_LP);
-        e = launch_mg_restrict(gf, gc, 0, kc, mg_box(g, l, MG_KC), 1, g->stream);
-        if (e == hipSuccess) e = launch_mg_restrict(gf, gc, 0, eta, mg_box(g, l, MG_ETA), g->mgp.eta_mean, g->stream);
-        if (e == hipSuccess) e = launch_mg_restrict(gf, gc, 0, mus, mg_box(g, l, MG_MUS), 0, g->stream);
-        if (e == hipSuccess) e = launch_mg_restrict(gf, gc, 0, lp, mg_box(g, l, MG_LP), 0, g->stream);
+        const double* tab[3] = {mg_tab(g, l - 1, 0, 0), mg_tab(g, l - 1, 1, 0), mg_tab(g, l - 1, 2, 0)};
+        double *sa = mg_scr(g, 0), *sb = mg_scr(g, 1);
+        e = launch_mg_restrict(gf, gc, kc, mg_box(g, l, MG_KC), 1, sa, sb, tab, g->stream);
+        if (e == hipSuccess)
+            e = launch_mg_restrict(gf, gc, eta, mg_box(g, l, MG_ETA), g->mgp.eta_mean, sa, sb, tab, g->stream);
+        if (e == hipSuccess) e = launch_mg_restrict(gf, gc, mus, mg_box(g, l, MG_MUS), 0, sa, sb, tab, g->stream);
+        if (e == hipSuccess) e = launch_mg_restrict(gf, gc, lp, mg_box(g, l, MG_LP), 0, sa, sb, tab, g->stream);
     }
     if (e != hipSuccess) return hip_fail(g, e, "multigrid coefficients");
     return PT_OK;

@@ -95,54 +95,6 @@ struct Ext {
 };
 __host__ __device__ inline Ext ext(const Geom& g) { return Ext{g.nx, g.ny, g.nz, g.P, g.S}; }
 
-// Restriction of one field of staggering (fx, fy, fz: face along that
-// axis).  mode 0: average, 1: harmonic average, 2: geometric average.
-// Walls' normal faces: 0.
-template <typename TS>
-__global__ __launch_bounds__(TB) void k_mg_restrict(Ext f, Ext c, bool fx, bool fy, bool fz, const TS* __restrict__ src,
-                                                    double* __restrict__ dst, int mode) {
-    const int ex = c.nx + fx, ey = c.ny + fy, ez = c.nz + fz;
-    const int64_t n = (int64_t)ex * ey * ez;
-    for (int64_t t = (int64_t)blockIdx.x * TB + threadIdx.x; t < n; t += (int64_t)gridDim.x * TB) {
-        const int I = (int)(t % ex), J = (int)((t / ex) % ey), K = (int)(t / ((int64_t)ex * ey));
-        const int64_t o = (int64_t)K * c.S + (int64_t)J * c.P + I;
-        if ((fx && (I == 0 || I == c.nx)) || (fy && (J == 0 || J == c.ny)) || (fz && (K == 0 || K == c.nz))) {
-            dst[o] = 0.0;
-            continue;
-        }
-        // the walls' normal faces are not equations
-        Taps tx;
-        taps(I, f.nx, c.nx, fx, fx, tx);
-        int yl, yh, zl, zh;
-        prange(J, f.ny, c.ny, fy, yl, yh);
-        prange(K, f.nz, c.nz, fz, zl, zh);
-        if (fy) { yl = max(yl, 1); yh = min(yh, f.ny - 1); }
-        if (fz) { zl = max(zl, 1); zh = min(zh, f.nz - 1); }
-        double s = 0.0, ws = 0.0;
-        for (int k = zl; k <= zh; ++k) {
-            const double wz = pweight(k, K, f.nz, c.nz, fz);
-            if (wz == 0.0) continue;
-            for (int j = yl; j <= yh; ++j) {
-                const double wy = pweight(j, J, f.ny, c.ny, fy) * wz;
-                if (wy == 0.0) continue;
-                const TS* row = src + (int64_t)k * f.S + (int64_t)j * f.P + tx.lo;
-                double r = 0.0;
-#pragma unroll
-                for (int q = 0; q < MAXT; ++q) {
-                    if (q < tx.n) {
-                        const double v = (double)row[q];
-                        r += tx.w[q] * (mode == 0 ? v : mode == 1 ? 1.0 / v : log(v));
-                    }
-                }
-                s += wy * r;
-                ws += wy;
-            }
-        }
-        ws *= tx.sum;
-        dst[o] = (ws > 0.0) ? (mode == 0 ? s / ws : mode == 1 ? ws / s : exp(s / ws)) : 0.0;
-    }
-}
-
 // One axis of the separable restriction.  The restriction is a tensor
 // product of one-dimensional rows, each normalised to weight sum 1, so it
 // runs as three passes (x, then y, then z), each reading its input once in
@@ -155,10 +107,12 @@ __global__ __launch_bounds__(TB) void k_mg_restrict(Ext f, Ext c, bool fx, bool 
 // thread divides its index.
 constexpr int GX = 64, GY = 4;
 
+// mean: 0 arithmetic; 1 harmonic, 2 geometric (the x pass averages 1/v or
+// ln v, the z pass maps the average back), so that the passes stay linear.
 template <typename TI>
 __global__ __launch_bounds__(GX * GY) void k_mg_r1(const TI* __restrict__ src, int64_t sP, int64_t sS,
                                                   double* __restrict__ dst, int64_t dP, int64_t dS, int ex, int ey,
-                                                  int axis, const double* __restrict__ tab) {
+                                                  int axis, const double* __restrict__ tab, int mean) {
     const int i = blockIdx.x * GX + threadIdx.x, j = blockIdx.y * GY + threadIdx.y, k = blockIdx.z;
     if (i < ex && j < ey) {
         const int64_t step = axis == 0 ? 1 : (axis == 1 ? sP : sS);
@@ -171,7 +125,12 @@ __global__ __launch_bounds__(GX * GY) void k_mg_r1(const TI* __restrict__ src, i
         double r = 0.0;
 #pragma unroll
         for (int q = 0; q < MAXT; ++q)
-            if (q < cnt) r += row[2 + q] * (double)src[base + q * step];
+            if (q < cnt) {
+                double v = (double)src[base + q * step];
+                if (axis == 0 && mean) v = mean == 1 ? 1.0 / v : log(v);
+                r += row[2 + q] * v;
+            }
+        if (axis == 2 && mean && cnt > 0) r = mean == 1 ? 1.0 / r : exp(r);
         dst[(int64_t)k * dS + (int64_t)j * dP + i] = r;
     }
 }
@@ -240,31 +199,23 @@ unsigned blocks_for(int64_t n) { return (unsigned)std::min<int64_t>((n + TB - 1)
 
 }  // namespace
 
-hipError_t launch_mg_restrict(const Geom& gf, const Geom& gc, int kind, const double* src, double* dst, int mean,
-                              hipStream_t s) {
-    const bool fx = kind == 1, fy = kind == 2, fz = kind == 3;
-    const int64_t n = (int64_t)(gc.nx + fx) * (gc.ny + fy) * (gc.nz + fz);
-    hipLaunchKernelGGL(k_mg_restrict<double>, dim3(blocks_for(n)), dim3(TB), 0, s, ext(gf), ext(gc), fx, fy, fz, src,
-                       dst, mean);
-    return hipGetLastError();
-}
-
 namespace {
 
 // The three passes of a separable restriction of an FP32 fine field
 // (scratch sa: (nz_f + 1) (ny_f + 1) P_c doubles, sb: (nz_f + 1) (ny_c + 1) P_c;
 // tab: the rows of the x, y, z axes for this field's staggering).
-hipError_t restrict_sep(const Geom& gf, const Geom& gc, int kind, const float* src, double* dst, double* sa,
-                        double* sb, const double* const tab[3], hipStream_t s) {
+template <typename TI>
+hipError_t restrict_sep(const Geom& gf, const Geom& gc, int kind, const TI* src, double* dst, double* sa,
+                        double* sb, const double* const tab[3], int mean, hipStream_t s) {
     const bool fx = kind == 1, fy = kind == 2, fz = kind == 3;
     const int64_t aS = gc.P * (int64_t)(gf.ny + 1), bS = gc.P * (int64_t)(gc.ny + 1);
     const dim3 blk(GX, GY);
-    hipLaunchKernelGGL(k_mg_r1<float>, grid3(gc.nx + fx, gf.ny + fy, gf.nz + fz), blk, 0, s, src, gf.P, gf.S, sa,
-                       gc.P, aS, gc.nx + fx, gf.ny + fy, 0, tab[0]);
+    hipLaunchKernelGGL(k_mg_r1<TI>, grid3(gc.nx + fx, gf.ny + fy, gf.nz + fz), blk, 0, s, src, gf.P, gf.S, sa,
+                       gc.P, aS, gc.nx + fx, gf.ny + fy, 0, tab[0], mean);
     hipLaunchKernelGGL(k_mg_r1<double>, grid3(gc.nx + fx, gc.ny + fy, gf.nz + fz), blk, 0, s, (const double*)sa,
-                       gc.P, aS, sb, gc.P, bS, gc.nx + fx, gc.ny + fy, 1, tab[1]);
+                       gc.P, aS, sb, gc.P, bS, gc.nx + fx, gc.ny + fy, 1, tab[1], mean);
     hipLaunchKernelGGL(k_mg_r1<double>, grid3(gc.nx + fx, gc.ny + fy, gc.nz + fz), blk, 0, s, (const double*)sb,
-                       gc.P, bS, dst, gc.P, gc.S, gc.nx + fx, gc.ny + fy, 2, tab[2]);
+                       gc.P, bS, dst, gc.P, gc.S, gc.nx + fx, gc.ny + fy, 2, tab[2], mean);
     return hipGetLastError();
 }
 
@@ -275,16 +226,21 @@ hipError_t launch_mg_taps(double* tab, int nf, int nc, int face, hipStream_t s) 
     return hipGetLastError();
 }
 
+hipError_t launch_mg_restrict(const Geom& gf, const Geom& gc, const double* src, double* dst, int mean, double* sa,
+                              double* sb, const double* const tab[3], hipStream_t s) {
+    return restrict_sep(gf, gc, 0, src, dst, sa, sb, tab, mean, s);
+}
+
 hipError_t launch_mg_restrict32(const Geom& gf, const Geom& gc, int kind, const float* src, double* dst,
                                 double* sa, double* sb, const double* const tab[3], hipStream_t s) {
-    return restrict_sep(gf, gc, kind, src, dst, sa, sb, tab, s);
+    return restrict_sep(gf, gc, kind, src, dst, sa, sb, tab, 0, s);
 }
 
 hipError_t launch_mg_restrict_fold(const Geom& gf, const Geom& gc, const float* rpt, const float* rpf, double* pto,
                                    double* pfo, const double m[4], double* sa, double* sb, const double* const tab[3],
                                    hipStream_t s) {
-    hipError_t e = restrict_sep(gf, gc, 0, rpt, pto, sa, sb, tab, s);
-    if (e == hipSuccess) e = restrict_sep(gf, gc, 0, rpf, pfo, sa, sb, tab, s);
+    hipError_t e = restrict_sep(gf, gc, 0, rpt, pto, sa, sb, tab, 0, s);
+    if (e == hipSuccess) e = restrict_sep(gf, gc, 0, rpf, pfo, sa, sb, tab, 0, s);
     if (e != hipSuccess) return e;
     const int64_t n = (int64_t)gc.nx * gc.ny * gc.nz;
     hipLaunchKernelGGL(k_mg_fold, dim3(blocks_for(n)), dim3(TB), 0, s, ext(gc), pto, pfo, m[0], m[1], m[2], m[3]);

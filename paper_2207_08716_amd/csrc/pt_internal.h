@@ -257,11 +257,11 @@ hipError_t launch_apply_correction(const Geom& g, const MixedPtrs& m, hipStream_
 
 // Multigrid transfers between a fine grid gf and its coarse grid gc
 // (mg_kernels.hip).  kind: 0 cells, 1/2/3 faces normal to x/y/z.
-// Restriction: averages (mean 0: arithmetic, 1: harmonic, 2: geometric)
-// of the fine values around each coarse point, zero on the walls' normal
-// faces.
-hipError_t launch_mg_restrict(const Geom& gf, const Geom& gc, int kind, const double* src, double* dst, int mean,
-                              hipStream_t s);
+// Restriction of a cell field: averages (mean 0: arithmetic, 1: harmonic,
+// 2: geometric) of the fine values around each coarse point, by the
+// separable passes below (their scratch and rows).
+hipError_t launch_mg_restrict(const Geom& gf, const Geom& gc, const double* src, double* dst, int mean, double* sa,
+                              double* sb, const double* const tab[3], hipStream_t s);
 // Normalised restriction rows of one axis (fine nf, coarse nc points; face:
 // faces normal to the axis): MG_TAB doubles per coarse index (first fine
 // index, count, MG_TAB - 2 weights), nc + face rows.
